@@ -1,0 +1,265 @@
+"""Throughput benchmark of the aging Metropolis hot path on one MI355X.
+
+Workload (one step = one pass of the whole path over the batch): the batched
+Viana-Bray configuration -- 256 Erdos-Renyi graphs (N = 65536, mean degree 4,
++-1 couplings) x 3 temperatures {0.6, 0.8, 1.2} x 2 replicas = 1536 chains --
+advanced by `--sweeps-per-step` Metropolis sweeps (snapshots at grid times on
+the device), followed by the measurement (bond sums, overlaps, int8-MFMA Gram
+matrices of all snapshots).  Inputs are synthetic and seeded; all state is in
+HBM before the timed region starts.
+
+Prints one JSON line: attempted single-spin updates per ns (the paper counts
+spin updates), plus the roofline of the dominant kernel (the VB sweep),
+secondary figures for the plain one-instance run and the SK configuration,
+and the CPU oracle timed on the host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "spin flips/ns at 1 GPU (VB, SK), batched vs plain; p50/p99 run latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def vb_bytes_per_sweep(descs, R, chains_per_unit):
+    """Algorithmic HBM bytes of one VB sweep: every work unit streams its
+    graph once (row starts 4 (N+1) B + entries 4 x 2M B); the spins stay in
+    LDS.  Units hold up to `chains_per_unit` chains of one graph."""
+    from paper_1906_11195_amd.workloads import VbDesc  # noqa: F401
+    graphs = {}
+    for d in descs:
+        key = (d.n, d.c, d.seed, d.graph_id)
+        graphs.setdefault(key, [d.n, 0])
+        graphs[key][1] += R
+    total = 0
+    for (n, c, _, _), (_, chains) in graphs.items():
+        m = math.floor(c * n / 2)
+        units = math.ceil(chains / chains_per_unit)
+        total += units * (4 * (n + 1) + 8 * m)
+    return total
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    f = math.floor(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def run_vb_batched(args, torch, sg, workloads):
+    descs = workloads.vb_batched()
+    R = 2
+    t_max = workloads.VB_BATCHED_SWEEPS
+    log("creating VB batched context (%d instances, %d chains)" % (len(descs), len(descs) * R))
+    ctx = sg.sg_create_vb(descs, t_max=t_max, chains_per_unit=args.chains_per_unit,
+                          threads_per_unit=args.threads)
+    stream = torch.cuda.current_stream()
+    S = args.sweeps_per_step
+    chains_per_unit = args.chains_per_unit or 6
+
+    def step():
+        sg.sg_sweep(ctx, S, stream)
+        return sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+
+    for w in range(args.warmup):
+        step()
+        log("warmup step %d done" % (w + 1))
+    torch.cuda.synchronize()
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    accepted0 = None
+    for k in range(args.steps):
+        ev0[k].record(stream)
+        sg.sg_sweep(ctx, S, stream)
+        ev1[k].record(stream)
+        res = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+        if accepted0 is None:
+            accepted0 = res["accepted"].sum()
+        log("step %d done" % (k + 1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sweep_ms = sum(a.elapsed_time(b) for a, b in zip(ev0, ev1))
+    elapsed = t1 - t0
+    n_total = sum(d.n for d in descs) * R
+    updates = n_total * S * args.steps
+    res = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+    sg.sg_free(ctx)
+    cap = max(1, min(4096, (1 << 36) // n_total))
+    launches_per_step = math.ceil(S / cap)
+    bytes_per_sweep = vb_bytes_per_sweep(descs, R, chains_per_unit)
+    launch_ms = sweep_ms / (args.steps * launches_per_step)
+    launch_bytes = bytes_per_sweep * S / launches_per_step
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    return dict(
+        value=updates / (elapsed * 1e9), elapsed=elapsed, updates=updates,
+        sweep_kernel_updates_per_ns=updates / (sweep_ms * 1e6),
+        accepted_per_ns=float(res["accepted"].sum() - accepted0) / (elapsed * 1e9) if accepted0 is not None else None,
+        roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                      kernel="vb_sweep_kernel", launch_ms=round(launch_ms, 4),
+                      bytes_per_launch=int(launch_bytes), bytes_per_update=round(bytes_per_sweep / n_total, 3)),
+        ms_per_step=elapsed * 1e3 / args.steps, t_done=res["t_done"])
+
+
+def run_vb_plain(args, torch, sg, workloads):
+    """Plain one-instance run (1024 spins, 2 replicas, 4096 sweeps): run latency."""
+    d = workloads.vb_plain()
+    lat = []
+    for rep in range(args.plain_runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = sg.sg_create_vb(d, t_max=workloads.VB_PLAIN_SWEEPS)
+        sg.sg_sweep(ctx, workloads.VB_PLAIN_SWEEPS)
+        sg.sg_measure(ctx, sg.MEASURE_OBS)
+        sg.sg_free(ctx)
+        lat.append(time.perf_counter() - t0)
+    upd = 1024 * 2 * workloads.VB_PLAIN_SWEEPS
+    return dict(workload="VB plain: N=1024, 2 replicas, T=0.8, 4096 sweeps (create + sweeps + measure)",
+                updates_per_ns=upd / (percentile(lat, 50) * 1e9),
+                p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3, runs=len(lat))
+
+
+def run_sk(args, torch, sg, workloads):
+    descs = workloads.sk_batch()
+    ctx = sg.sg_create_sk(descs, t_max=workloads.SK_SWEEPS)
+    stream = torch.cuda.current_stream()
+    sg.sg_sweep(ctx, 64, stream)          # warm-up window (includes one recompute)
+    torch.cuda.synchronize()
+    a0 = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)["accepted"].sum()
+    t0 = time.perf_counter()
+    sg.sg_sweep(ctx, args.sk_sweeps, stream)
+    res = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sg.sg_free(ctx)
+    upd = 64 * 2 * 4096 * args.sk_sweeps
+    return dict(workload="SK: 64 samples x 2 replicas, N=4096, T=0.5, sweeps 64..%d" % (64 + args.sk_sweeps),
+                updates_per_ns=upd / (el * 1e9),
+                accepted_fraction=float(res["accepted"].sum() - a0) / upd, sweeps=args.sk_sweeps)
+
+
+def run_cpu_baseline(args, workloads):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    `threads` instances of the batched configuration (N = 65536, 2 replicas)
+    for a few sweeps each, one instance per host thread."""
+    import concurrent.futures as cf
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(16, cores))
+    descs = workloads.vb_batched()[:threads]
+    graphs = [oracle.vb_instance(d.n, d.c, d.seed, d.graph_id) for d in descs]
+    # calibrate on one sweep of one instance
+    t0 = time.perf_counter()
+    eu, ev, J = graphs[0]
+    oracle.vb_run(descs[0].n, eu, ev, J, descs[0].T, descs[0].seed, descs[0].instance_id, 2, 1, 1)
+    one = time.perf_counter() - t0
+    sweeps = int(max(2, min(4096, args.cpu_seconds / max(one, 1e-3))))
+
+    def job(i):
+        d = descs[i]
+        eu, ev, J = graphs[i]
+        oracle.vb_run(d.n, eu, ev, J, d.T, d.seed, d.instance_id, 2, sweeps, sweeps)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(job, range(threads)))
+    el = time.perf_counter() - t0
+    upd = threads * 2 * 65536 * sweeps
+    return dict(value=upd / (el * 1e9), unit="attempted spin updates/ns", cores=threads, kind="oracle",
+                sample="%d instances of the batched VB workload (N=65536, 2 replicas), %d sweeps each, "
+                       "one instance per thread; %.1f s" % (threads, sweeps, el))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sweeps-per-step", type=int, default=2048)
+    ap.add_argument("--chains-per-unit", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--plain-runs", type=int, default=20)
+    ap.add_argument("--sk-sweeps", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-vb", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(batches would shard by instance with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1906_11195_amd as sg
+    from paper_1906_11195_amd import workloads
+
+    torch.cuda.set_device(0)
+    sg.library()
+    vb = run_vb_batched(args, torch, sg, workloads)
+    log("VB batched: %.1f updates/ns" % vb["value"])
+    plain = sk = None
+    if not args.only_vb:
+        plain = run_vb_plain(args, torch, sg, workloads)
+        log("VB plain: p50 %.2f ms" % plain["p50_ms"])
+        sk = run_sk(args, torch, sg, workloads)
+        log("SK: %.2f updates/ns" % sk["updates_per_ns"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = run_cpu_baseline(args, workloads)
+        log("cpu oracle: %.4f updates/ns on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": METRIC,
+        "value": round(vb["value"], 3),
+        "unit": "attempted spin updates/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(vb["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "VB batched: 256 ER graphs (N=65536, c=4, J=+-1) x T{0.6,0.8,1.2} x 2 replicas "
+                        "= 1536 chains; step = %d sweeps + observables + int8-MFMA Gram" % args.sweeps_per_step,
+            "sweeps_per_step": args.sweeps_per_step,
+            "chains": 1536,
+            "spins_per_chain": 65536,
+            "parallelism": "1 GPU, one workgroup per graph (chains sharing its stream)",
+        },
+        "accepted_flips_per_ns": vb["accepted_per_ns"],
+        "sweep_kernel_updates_per_ns": round(vb["sweep_kernel_updates_per_ns"], 3),
+        "roofline": vb["roofline"],
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "sk": sk,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,1060 @@
+// Host runtime of the library: instance builder (graph, colouring, sweep
+// order, adjacency in sweep order, threshold tables), device memory layout,
+// kernel launches and the C ABI declared in include/sg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "sg.h"
+#include "sg_internal.h"
+#include "sg_philox.h"
+
+using namespace sg;
+
+namespace {
+
+struct Fail {
+    sg_status code;
+};
+
+[[noreturn]] void fail(sg_status s) { throw Fail{s}; }
+
+void hip_check(hipError_t e)
+{
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) fail(SG_ENOMEM);
+        fail(SG_EDEVICE);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Thresholds: thr[x] = floor(2^32 exp(-beta dE)), dE = 2 x s (Metropolis).
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+uint64_t threshold(double T, double s, int64_t x)
+{
+    const double beta = 1.0 / T;
+    const double dE = 2.0 * (double)x * s;
+    return (uint64_t)std::floor(std::ldexp(std::exp(-beta * dE), 32));
+}
+
+// ---------------------------------------------------------------------------
+// VB instance tables.
+// ---------------------------------------------------------------------------
+struct VbGraph {
+    int64_t n = 0;
+    std::vector<int32_t> eu, ev;     // edges in acceptance / given order
+    std::vector<int8_t> J;
+    std::vector<int32_t> colour;     // per vertex
+    std::vector<int32_t> order;      // vertex at each position
+    std::vector<int32_t> row;        // [n+1], sweep order
+    std::vector<uint32_t> ent;       // [2m]
+    std::vector<int32_t> cls;        // [ncls+1]
+    int32_t ncls = 0;
+    int32_t max_degree = 0;
+};
+
+// G(N, M) from the GRAPH stream (rejecting self-loops and repeated pairs).
+void er_generate(VbGraph& g, int64_t m, uint64_t seed, uint32_t graph_id)
+{
+    const uint64_t n = (uint64_t)g.n;
+    g.eu.resize((size_t)m);
+    g.ev.resize((size_t)m);
+    g.J.resize((size_t)m);
+    std::unordered_set<uint64_t> seen;
+    seen.reserve((size_t)m * 2 + 16);
+    int64_t k = 0;
+    for (uint64_t a = 0; k < m; ++a) {
+        const U4 w = philox_stream(seed, (uint32_t)a, (uint32_t)(a >> 32), kDomGraph, 0u, graph_id);
+        const uint64_t u = ((uint64_t)w.x * n) >> 32;
+        const uint64_t v = ((uint64_t)w.y * n) >> 32;
+        if (u == v) continue;
+        const uint64_t key = u < v ? (u << 32) | v : (v << 32) | u;
+        if (!seen.insert(key).second) continue;
+        g.eu[(size_t)k] = (int32_t)u;
+        g.ev[(size_t)k] = (int32_t)v;
+        g.J[(size_t)k] = (w.z & 1u) ? (int8_t)-1 : (int8_t)1;
+        ++k;
+    }
+}
+
+// Greedy colouring, sweep order and the adjacency in sweep order.
+void vb_tables(VbGraph& g)
+{
+    const int64_t n = g.n;
+    const size_t m = g.eu.size();
+    std::vector<int32_t> deg((size_t)n, 0);
+    for (size_t e = 0; e < m; ++e) {
+        deg[(size_t)g.eu[e]]++;
+        deg[(size_t)g.ev[e]]++;
+    }
+    std::vector<int64_t> vstart((size_t)n + 1, 0);
+    for (int64_t v = 0; v < n; ++v) vstart[(size_t)v + 1] = vstart[(size_t)v] + deg[(size_t)v];
+    std::vector<int32_t> vn(2 * m);
+    std::vector<int8_t> vj(2 * m);
+    std::vector<int64_t> fill(vstart.begin(), vstart.end() - 1);
+    for (size_t e = 0; e < m; ++e) {
+        const int32_t u = g.eu[e], v = g.ev[e];
+        vn[(size_t)fill[(size_t)u]] = v;
+        vj[(size_t)fill[(size_t)u]++] = g.J[e];
+        vn[(size_t)fill[(size_t)v]] = u;
+        vj[(size_t)fill[(size_t)v]++] = g.J[e];
+    }
+    g.max_degree = 0;
+    for (int64_t v = 0; v < n; ++v) g.max_degree = std::max(g.max_degree, deg[(size_t)v]);
+
+    // colour(v) = smallest colour absent among neighbours u < v
+    g.colour.assign((size_t)n, 0);
+    std::vector<int64_t> stamp((size_t)g.max_degree + 2, -1);
+    int32_t ncls = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        for (int64_t a = vstart[(size_t)v]; a < vstart[(size_t)v + 1]; ++a) {
+            const int32_t u = vn[(size_t)a];
+            if (u < v) {
+                const int32_t cu = g.colour[(size_t)u];
+                if (cu <= g.max_degree) stamp[(size_t)cu] = v;
+            }
+        }
+        int32_t c = 0;
+        while (stamp[(size_t)c] == v) ++c;
+        g.colour[(size_t)v] = c;
+        ncls = std::max(ncls, c + 1);
+    }
+    g.ncls = ncls;
+
+    // positions: class by class, increasing id inside a class (counting sort)
+    g.cls.assign((size_t)ncls + 1, 0);
+    for (int64_t v = 0; v < n; ++v) g.cls[(size_t)g.colour[(size_t)v] + 1]++;
+    for (int32_t c = 0; c < ncls; ++c) g.cls[(size_t)c + 1] += g.cls[(size_t)c];
+    std::vector<int32_t> next(g.cls.begin(), g.cls.end() - 1);
+    g.order.assign((size_t)n, 0);
+    std::vector<int32_t> pos((size_t)n);
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t p = next[(size_t)g.colour[(size_t)v]]++;
+        g.order[(size_t)p] = (int32_t)v;
+        pos[(size_t)v] = p;
+    }
+    g.row.assign((size_t)n + 1, 0);
+    g.ent.resize(2 * m);
+    int64_t e = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        const int32_t v = g.order[(size_t)p];
+        g.row[(size_t)p] = (int32_t)e;
+        for (int64_t a = vstart[(size_t)v]; a < vstart[(size_t)v + 1]; ++a)
+            g.ent[(size_t)e++] = (uint32_t)pos[(size_t)vn[(size_t)a]] |
+                                 (vj[(size_t)a] < 0 ? 0x80000000u : 0u);
+    }
+    g.row[(size_t)n] = (int32_t)e;
+}
+
+bool finite_nonneg_T(double T) { return !(T < 0.0) && !std::isnan(T); }
+
+void check_vb_desc(const sg_vb_desc& d)
+{
+    if (d.n < 2 || d.n > (1 << 20)) fail(d.n > (1 << 20) ? SG_ENOTSUP : SG_EINVAL);
+    if (!finite_nonneg_T(d.T)) fail(SG_EINVAL);
+    if (d.n_replicas < 1 || d.n_replicas > kVbMaxChains) fail(SG_EINVAL);
+    if (d.start < SG_START_RANDOM || d.start > SG_START_GIVEN) fail(SG_EINVAL);
+    if (d.start == SG_START_GIVEN) {
+        if (!d.s0) fail(SG_EINVAL);
+        for (int64_t i = 0; i < d.n * d.n_replicas; ++i)
+            if (d.s0[i] != 1 && d.s0[i] != -1) fail(SG_EINVAL);
+    }
+    if (d.edges) {
+        if (d.n_edges < 0 || !d.J || d.n_edges > d.n * (d.n - 1) / 2) fail(SG_EINVAL);
+        std::unordered_set<uint64_t> seen;
+        seen.reserve((size_t)d.n_edges * 2 + 1);
+        for (int64_t e = 0; e < d.n_edges; ++e) {
+            const int64_t u = d.edges[2 * e], v = d.edges[2 * e + 1];
+            if (u < 0 || v < 0 || u >= d.n || v >= d.n || u == v) fail(SG_EINVAL);
+            if (d.J[e] != 1 && d.J[e] != -1) fail(SG_EINVAL);
+            const uint64_t key = u < v ? ((uint64_t)u << 32) | (uint64_t)v
+                                       : ((uint64_t)v << 32) | (uint64_t)u;
+            if (!seen.insert(key).second) fail(SG_EINVAL);
+        }
+    } else {
+        if (!(d.c >= 0.0) || std::isinf(d.c)) fail(SG_EINVAL);
+        const double m = std::floor(d.c * (double)d.n / 2.0);
+        if (m > (double)(d.n * (d.n - 1) / 2)) fail(SG_EINVAL);
+    }
+}
+
+void build_vb_graph(const sg_vb_desc& d, VbGraph& g)
+{
+    g.n = d.n;
+    if (d.edges) {
+        g.eu.resize((size_t)d.n_edges);
+        g.ev.resize((size_t)d.n_edges);
+        g.J.assign(d.J, d.J + d.n_edges);
+        for (int64_t e = 0; e < d.n_edges; ++e) {
+            g.eu[(size_t)e] = d.edges[2 * e];
+            g.ev[(size_t)e] = d.edges[2 * e + 1];
+        }
+    } else {
+        const int64_t m = (int64_t)std::floor(d.c * (double)d.n / 2.0);
+        er_generate(g, m, d.seed, d.graph_id);
+    }
+    vb_tables(g);
+    if (g.max_degree >= kVbXMax) fail(SG_ENOTSUP);
+}
+
+void check_sk_desc(const sg_sk_desc& d)
+{
+    if (d.n < 2 || d.n > 32768) fail(d.n > 32768 ? SG_ENOTSUP : SG_EINVAL);
+    if (!finite_nonneg_T(d.T)) fail(SG_EINVAL);
+    if (d.n_replicas < 1 || d.n_replicas > kVbMaxChains) fail(SG_EINVAL);
+    if (d.start < SG_START_RANDOM || d.start > SG_START_GIVEN) fail(SG_EINVAL);
+    if (d.recompute_period < 0) fail(SG_EINVAL);
+    if (d.start == SG_START_GIVEN) {
+        if (!d.s0) fail(SG_EINVAL);
+        for (int64_t i = 0; i < d.n * d.n_replicas; ++i)
+            if (d.s0[i] != 1 && d.s0[i] != -1) fail(SG_EINVAL);
+    }
+    if (d.J) {
+        const int64_t n = d.n;
+        for (int64_t i = 0; i < n; ++i) {
+            if (d.J[i * n + i] != 0) fail(SG_EINVAL);
+            for (int64_t j = i + 1; j < n; ++j) {
+                const int8_t a = d.J[i * n + j];
+                if ((a != 1 && a != -1) || d.J[j * n + i] != a) fail(SG_EINVAL);
+            }
+        }
+    }
+}
+
+void sk_generate(int64_t n, uint64_t seed, uint32_t graph_id, int8_t* J)
+{
+    for (int64_t i = 0; i < n; ++i) J[i * n + i] = 0;
+    // one Philox block covers 128 consecutive idx = i N + j
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = i + 1;
+        while (j < n) {
+            const uint64_t idx = (uint64_t)i * (uint64_t)n + (uint64_t)j;
+            const uint64_t blk = idx >> 7;
+            const U4 w = philox_stream(seed, (uint32_t)blk, (uint32_t)(idx >> 39), kDomCoupling, 0u,
+                                       graph_id);
+            const uint64_t blk_end = (blk + 1) << 7;
+            for (; j < n && (uint64_t)i * (uint64_t)n + (uint64_t)j < blk_end; ++j) {
+                const uint64_t id2 = (uint64_t)i * (uint64_t)n + (uint64_t)j;
+                const uint32_t bit = (word_of(w, (uint32_t)((id2 >> 5) & 3u)) >> (id2 & 31u)) & 1u;
+                const int8_t v = bit ? (int8_t)-1 : (int8_t)1;
+                J[i * n + j] = v;
+                J[j * n + i] = v;
+            }
+        }
+    }
+}
+
+template <class F>
+void parallel_for(size_t count, F&& f)
+{
+    const size_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const size_t nt = std::min(count, hw);
+    if (nt <= 1) {
+        for (size_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    std::atomic<int> err{0};
+    std::vector<std::thread> th;
+    for (size_t t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (;;) {
+                const size_t i = next.fetch_add(1);
+                if (i >= count) break;
+                try {
+                    f(i);
+                } catch (const Fail& e) {
+                    err.store(e.code);
+                } catch (...) {
+                    err.store(SG_ENOMEM);
+                }
+            }
+        });
+    for (auto& x : th) x.join();
+    if (err.load() != 0) fail(err.load());
+}
+
+int32_t grid_size(int64_t t_max)
+{
+    int32_t k = 1;
+    for (int64_t t = 1; t <= t_max; t <<= 1) ++k;
+    return k;
+}
+
+// Device arena: one allocation carved into aligned pieces.
+struct Arena {
+    size_t size = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t off = size;
+        size += (bytes + 255) & ~(size_t)255;
+        return off;
+    }
+};
+
+}  // namespace
+
+struct sg_ctx {
+    int kind = 0;   // 0 VB, 1 SK
+    int device = 0;
+    sg_alloc_fn alloc = nullptr;
+    sg_free_fn freef = nullptr;
+    void* user = nullptr;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    hipStream_t last_stream = nullptr;
+    int32_t count = 0, R = 0, K = 0, n_chains = 0;
+    int64_t t_max = 0, t_done = 0;
+    std::vector<int64_t> times;
+    std::vector<int64_t> n_of;            // spins per instance
+    // VB
+    std::vector<int32_t> group_of_inst;
+    std::vector<std::vector<int32_t>> order_of_group;
+    std::vector<VbUnit> units;
+    VbUnit* units_d = nullptr;
+    int32_t* unit_chain_ids_d = nullptr;
+    std::vector<std::pair<int32_t, int32_t>> chain_loc;   // chain -> (unit, slot)
+    int vb_threads = 256;
+    size_t vb_lds = 0, bond_lds = 0;
+    int64_t updates_per_sweep = 0;
+    // SK
+    std::vector<SkChain> sk;
+    SkChain* sk_d = nullptr;
+    std::vector<SkSample> sks;
+    SkSample* sks_d = nullptr;
+    int sk_max_n = 0;
+    size_t sk_lds = 0;
+    int period = 64;
+    int* err_d = nullptr;
+    int sk_threads = 256;
+    // measurement
+    MeasureChain* mc_d = nullptr;
+    int32_t* pairs_d = nullptr;
+    int n_pairs = 0;
+    int max_words = 0;
+    long long* bond_d = nullptr;
+    long long* overlap_d = nullptr;
+    long long* gram_d = nullptr;
+    unsigned long long* acc_d = nullptr;
+
+    void* dev_alloc(size_t bytes)
+    {
+        void* p = nullptr;
+        if (alloc) {
+            p = alloc(bytes, user);
+            if (!p) fail(SG_ENOMEM);
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? SG_ENOMEM : SG_EDEVICE);
+        }
+        return p;
+    }
+    void release()
+    {
+        if (arena) {
+            if (alloc && freef) freef(arena, arena_bytes, user);
+            else if (!alloc) (void)hipFree(arena);
+            arena = nullptr;
+        }
+    }
+    template <class T>
+    T* at(size_t off) { return reinterpret_cast<T*>(static_cast<char*>(arena) + off); }
+    int32_t k_done() const
+    {
+        int32_t k = 0;
+        for (int64_t t : times)
+            if (t <= t_done) ++k;
+        return k;
+    }
+};
+
+namespace {
+
+void setup_common(sg_ctx* c, const sg_opts* o)
+{
+    c->t_max = o ? o->t_max : 0;
+    if (c->t_max < 0 || c->t_max >= (int64_t)1 << 31) fail(SG_EINVAL);
+    c->K = grid_size(c->t_max);
+    c->times.push_back(0);
+    for (int64_t t = 1; t <= c->t_max; t <<= 1) c->times.push_back(t);
+    if (o) {
+        c->alloc = o->alloc;
+        c->freef = o->free;
+        c->user = o->user;
+        if ((o->alloc == nullptr) != (o->free == nullptr)) fail(SG_EINVAL);
+        if (o->threads_per_unit != 0 &&
+            (o->threads_per_unit < 64 || o->threads_per_unit > 1024 || o->threads_per_unit % 64))
+            fail(SG_EINVAL);
+        if (o->chains_per_unit < 0 || o->chains_per_unit > kVbMaxChains) fail(SG_EINVAL);
+    }
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0) fail(SG_EDEVICE);
+    hip_check(hipGetDevice(&c->device));
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, c->device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) fail(SG_EDEVICE);
+}
+
+std::vector<uint32_t> pack_given(const int8_t* s0, int64_t n, const std::vector<int32_t>* order)
+{
+    std::vector<uint32_t> bits((size_t)((n + 31) / 32), 0u);
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t v = order ? (*order)[(size_t)p] : p;
+        if (s0[v] == -1) bits[(size_t)(p >> 5)] |= 1u << (p & 31);
+    }
+    return bits;
+}
+
+void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
+{
+    c->kind = 0;
+    c->count = count;
+    c->R = d[0].n_replicas;
+    for (int32_t i = 0; i < count; ++i) {
+        check_vb_desc(d[i]);
+        if (d[i].n_replicas != c->R) fail(SG_EINVAL);
+    }
+    setup_common(c, o);
+    c->n_chains = count * c->R;
+
+    // group instances that share a generated graph
+    struct Key {
+        int64_t n;
+        uint64_t cbits, seed;
+        uint32_t gid;
+        bool operator==(const Key& k) const
+        {
+            return n == k.n && cbits == k.cbits && seed == k.seed && gid == k.gid;
+        }
+    };
+    struct KeyHash {
+        size_t operator()(const Key& k) const
+        {
+            return std::hash<uint64_t>()((uint64_t)k.n * 0x9E3779B97F4A7C15ull ^ k.cbits ^
+                                         (k.seed << 1) ^ ((uint64_t)k.gid << 17));
+        }
+    };
+    std::unordered_map<Key, int32_t, KeyHash> gid_of;
+    std::vector<int32_t> first_inst;   // representative desc per group
+    c->group_of_inst.resize((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        if (d[i].edges) {
+            c->group_of_inst[(size_t)i] = (int32_t)first_inst.size();
+            first_inst.push_back(i);
+            continue;
+        }
+        uint64_t cb;
+        std::memcpy(&cb, &d[i].c, 8);
+        Key k{d[i].n, cb, d[i].seed, d[i].graph_id};
+        auto it = gid_of.find(k);
+        if (it == gid_of.end()) {
+            it = gid_of.emplace(k, (int32_t)first_inst.size()).first;
+            first_inst.push_back(i);
+        }
+        c->group_of_inst[(size_t)i] = it->second;
+    }
+    const size_t n_groups = first_inst.size();
+    std::vector<VbGraph> graphs(n_groups);
+    parallel_for(n_groups, [&](size_t gi) { build_vb_graph(d[first_inst[gi]], graphs[gi]); });
+
+    // chains of each group, then work units
+    std::vector<std::vector<int32_t>> chains_of(n_groups);
+    for (int32_t i = 0; i < count; ++i)
+        for (int32_t r = 0; r < c->R; ++r)
+            chains_of[(size_t)c->group_of_inst[(size_t)i]].push_back(i * c->R + r);
+    const int32_t want = o && o->chains_per_unit ? o->chains_per_unit : kVbMaxChains;
+    const size_t lds_cap = 160 * 1024 - 1024;
+
+    struct UnitPlan {
+        int32_t group;
+        std::vector<int32_t> chains;
+        int32_t rpad;
+    };
+    std::vector<UnitPlan> plan;
+    for (size_t gi = 0; gi < n_groups; ++gi) {
+        const int64_t n = graphs[gi].n;
+        int32_t per = std::min<int32_t>(want, (int32_t)chains_of[gi].size());
+        auto rpad_of = [](int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; };
+        while (per > 1 && vb_lds_bytes((int32_t)n, rpad_of(per)) > lds_cap) --per;
+        if (vb_lds_bytes((int32_t)n, rpad_of(per)) > lds_cap) fail(SG_ENOTSUP);
+        const auto& ch = chains_of[gi];
+        for (size_t a = 0; a < ch.size(); a += (size_t)per) {
+            UnitPlan u;
+            u.group = (int32_t)gi;
+            u.chains.assign(ch.begin() + (long)a, ch.begin() + (long)std::min(ch.size(), a + (size_t)per));
+            u.rpad = rpad_of((int32_t)u.chains.size());
+            plan.push_back(std::move(u));
+        }
+    }
+
+    // device layout
+    Arena A;
+    std::vector<size_t> off_row(n_groups), off_ent(n_groups), off_cls(n_groups);
+    for (size_t gi = 0; gi < n_groups; ++gi) {
+        off_row[gi] = A.take(graphs[gi].row.size() * 4);
+        off_ent[gi] = A.take(std::max<size_t>(1, graphs[gi].ent.size()) * 4);
+        off_cls[gi] = A.take(graphs[gi].cls.size() * 4);
+    }
+    std::vector<size_t> off_state(plan.size());
+    for (size_t u = 0; u < plan.size(); ++u) {
+        const int64_t n = graphs[(size_t)plan[u].group].n;
+        off_state[u] = A.take((size_t)((n * plan[u].rpad + 31) / 32) * 4);
+    }
+    std::vector<size_t> off_snap((size_t)c->n_chains), off_given((size_t)c->n_chains, 0);
+    c->n_of.resize((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        c->n_of[(size_t)i] = d[i].n;
+        const size_t wn = (size_t)((d[i].n + 31) / 32);
+        for (int32_t r = 0; r < c->R; ++r) {
+            off_snap[(size_t)(i * c->R + r)] = A.take(wn * (size_t)c->K * 4);
+            if (d[i].start == SG_START_GIVEN) off_given[(size_t)(i * c->R + r)] = A.take(wn * 4);
+        }
+        c->max_words = std::max(c->max_words, (int)wn);
+    }
+    const size_t off_units = A.take(plan.size() * sizeof(VbUnit));
+    const size_t off_ids = A.take(plan.size() * kVbMaxChains * 4);
+    const size_t off_mc = A.take((size_t)c->n_chains * sizeof(MeasureChain));
+    c->n_pairs = count * c->R * (c->R - 1) / 2;
+    const size_t off_pairs = A.take((size_t)std::max(1, c->n_pairs) * 8);
+    const size_t off_bond = A.take((size_t)c->n_chains * c->K * 8);
+    const size_t off_ovl = A.take((size_t)std::max(1, c->n_pairs) * c->K * 8);
+    const size_t off_gram = A.take((size_t)c->n_chains * c->K * c->K * 8);
+    const size_t off_acc = A.take((size_t)c->n_chains * 8);
+
+    c->arena_bytes = A.size;
+    c->arena = c->dev_alloc(A.size);
+
+    // uploads
+    for (size_t gi = 0; gi < n_groups; ++gi) {
+        const VbGraph& g = graphs[gi];
+        hip_check(hipMemcpy(c->at<void>(off_row[gi]), g.row.data(), g.row.size() * 4, hipMemcpyHostToDevice));
+        if (!g.ent.empty())
+            hip_check(hipMemcpy(c->at<void>(off_ent[gi]), g.ent.data(), g.ent.size() * 4, hipMemcpyHostToDevice));
+        hip_check(hipMemcpy(c->at<void>(off_cls[gi]), g.cls.data(), g.cls.size() * 4, hipMemcpyHostToDevice));
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        if (d[i].start != SG_START_GIVEN) continue;
+        const VbGraph& g = graphs[(size_t)c->group_of_inst[(size_t)i]];
+        for (int32_t r = 0; r < c->R; ++r) {
+            const auto bits = pack_given(d[i].s0 + (int64_t)r * d[i].n, d[i].n, &g.order);
+            hip_check(hipMemcpy(c->at<void>(off_given[(size_t)(i * c->R + r)]), bits.data(), bits.size() * 4,
+                                hipMemcpyHostToDevice));
+        }
+    }
+
+    c->units.resize(plan.size());
+    std::vector<int32_t> ids(plan.size() * kVbMaxChains, 0);
+    c->chain_loc.resize((size_t)c->n_chains);
+    int max_threads = 64;
+    c->updates_per_sweep = 0;
+    for (size_t u = 0; u < plan.size(); ++u) {
+        const VbGraph& g = graphs[(size_t)plan[u].group];
+        VbUnit U;
+        std::memset(&U, 0, sizeof(U));
+        U.row = c->at<int32_t>(off_row[(size_t)plan[u].group]);
+        U.ent = c->at<uint32_t>(off_ent[(size_t)plan[u].group]);
+        U.cls = c->at<int32_t>(off_cls[(size_t)plan[u].group]);
+        U.state = c->at<uint32_t>(off_state[u]);
+        U.n = (int32_t)g.n;
+        U.ncls = g.ncls;
+        U.nch = (int32_t)plan[u].chains.size();
+        U.rpad = plan[u].rpad;
+        U.state_words = (int32_t)((g.n * U.rpad + 31) / 32);
+        U.words_n = (int32_t)((g.n + 31) / 32);
+        for (int32_t k = 0; k < U.nch; ++k) {
+            const int32_t ch = plan[u].chains[(size_t)k];
+            const int32_t i = ch / c->R, r = ch % c->R;
+            U.snap[k] = c->at<uint32_t>(off_snap[(size_t)ch]);
+            U.accepted[k] = c->at<unsigned long long>(off_acc) + ch;
+            U.seed[k] = d[i].seed;
+            U.inst[k] = d[i].instance_id;
+            U.rep[k] = (uint32_t)r;
+            U.init_mode[k] = d[i].start;
+            U.given[k] = d[i].start == SG_START_GIVEN ? c->at<uint32_t>(off_given[(size_t)ch]) : nullptr;
+            for (int32_t x = 0; x < kVbXMax; ++x) {
+                const uint64_t th = x == 0 ? (uint64_t)1 << 32 : threshold(d[i].T, 1.0, x);
+                U.thr_hi[k][x] = (uint32_t)(th >> 16);
+                U.thr_lo[k][x] = (uint32_t)(th & 0xffffu);
+            }
+            ids[u * kVbMaxChains + (size_t)k] = ch;
+            c->chain_loc[(size_t)ch] = {(int32_t)u, k};
+        }
+        c->units[u] = U;
+        const int64_t groups8 = (g.n + 7) / 8;
+        max_threads = std::max<int>(max_threads, (int)std::min<int64_t>(1024, ((groups8 + 63) / 64) * 64));
+        c->vb_lds = std::max(c->vb_lds, vb_lds_bytes(U.n, U.rpad));
+        c->bond_lds = std::max(c->bond_lds, (size_t)(((U.nch * U.words_n + 1) & ~1) * 4 + kVbMaxChains * 8));
+        c->updates_per_sweep += g.n * U.nch;
+    }
+    c->vb_threads = o && o->threads_per_unit ? o->threads_per_unit : max_threads;
+    c->order_of_group.resize(n_groups);
+    for (size_t gi = 0; gi < n_groups; ++gi) c->order_of_group[gi] = std::move(graphs[gi].order);
+
+    std::vector<MeasureChain> mc((size_t)c->n_chains);
+    for (int32_t ch = 0; ch < c->n_chains; ++ch) {
+        const int64_t n = c->n_of[(size_t)(ch / c->R)];
+        mc[(size_t)ch] = MeasureChain{c->at<uint32_t>(off_snap[(size_t)ch]), (int32_t)((n + 31) / 32), (int32_t)n};
+    }
+    std::vector<int32_t> pairs;
+    for (int32_t i = 0; i < count; ++i)
+        for (int32_t a = 0; a < c->R; ++a)
+            for (int32_t b = a + 1; b < c->R; ++b) {
+                pairs.push_back(i * c->R + a);
+                pairs.push_back(i * c->R + b);
+            }
+    c->units_d = c->at<VbUnit>(off_units);
+    c->unit_chain_ids_d = c->at<int32_t>(off_ids);
+    c->mc_d = c->at<MeasureChain>(off_mc);
+    c->pairs_d = c->at<int32_t>(off_pairs);
+    c->bond_d = c->at<long long>(off_bond);
+    c->overlap_d = c->at<long long>(off_ovl);
+    c->gram_d = c->at<long long>(off_gram);
+    c->acc_d = c->at<unsigned long long>(off_acc);
+    hip_check(hipMemcpy(c->units_d, c->units.data(), c->units.size() * sizeof(VbUnit), hipMemcpyHostToDevice));
+    hip_check(hipMemcpy(c->unit_chain_ids_d, ids.data(), ids.size() * 4, hipMemcpyHostToDevice));
+    hip_check(hipMemcpy(c->mc_d, mc.data(), mc.size() * sizeof(MeasureChain), hipMemcpyHostToDevice));
+    if (!pairs.empty())
+        hip_check(hipMemcpy(c->pairs_d, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
+    hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
+    hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
+    hip_check(vb_init(c->units_d, (int)c->units.size(), 256, 0, nullptr));
+    hip_check(hipDeviceSynchronize());
+}
+
+void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
+{
+    c->kind = 1;
+    c->count = count;
+    c->R = d[0].n_replicas;
+    c->period = d[0].recompute_period ? d[0].recompute_period : 64;
+    for (int32_t i = 0; i < count; ++i) {
+        check_sk_desc(d[i]);
+        if (d[i].n_replicas != c->R) fail(SG_EINVAL);
+        if ((d[i].recompute_period ? d[i].recompute_period : 64) != c->period) fail(SG_EINVAL);
+    }
+    setup_common(c, o);
+    c->n_chains = count * c->R;
+    c->n_of.resize((size_t)count);
+
+    // samples sharing a generated coupling matrix
+    std::unordered_map<uint64_t, int32_t> share;
+    std::vector<int32_t> jslot((size_t)count);
+    std::vector<int32_t> jrep;   // representative instance per matrix
+    for (int32_t i = 0; i < count; ++i) {
+        c->n_of[(size_t)i] = d[i].n;
+        if (d[i].J) {
+            jslot[(size_t)i] = (int32_t)jrep.size();
+            jrep.push_back(i);
+            continue;
+        }
+        const uint64_t key = ((uint64_t)d[i].n * 0x9E3779B97F4A7C15ull) ^ (d[i].seed * 0xC2B2AE3D27D4EB4Full) ^
+                             ((uint64_t)d[i].graph_id << 1);
+        auto it = share.find(key);
+        if (it != share.end()) {
+            const sg_sk_desc& r = d[jrep[(size_t)it->second]];
+            if (r.n == d[i].n && r.seed == d[i].seed && r.graph_id == d[i].graph_id) {
+                jslot[(size_t)i] = it->second;
+                continue;
+            }
+        }
+        share[key] = (int32_t)jrep.size();
+        jslot[(size_t)i] = (int32_t)jrep.size();
+        jrep.push_back(i);
+    }
+
+    std::vector<std::vector<uint64_t>> thr((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        const double s = 1.0 / std::sqrt((double)d[i].n);
+        auto& t = thr[(size_t)i];
+        t.push_back((uint64_t)1 << 32);
+        for (int64_t x = 1; x < d[i].n; ++x) {
+            const uint64_t v = threshold(d[i].T, s, x);
+            if (v == 0) break;
+            t.push_back(v);
+        }
+    }
+
+    Arena A;
+    std::vector<size_t> off_J(jrep.size());
+    for (size_t j = 0; j < jrep.size(); ++j) {
+        const int64_t n = d[jrep[j]].n;
+        off_J[j] = A.take((size_t)(n * n));
+    }
+    std::vector<size_t> off_thr((size_t)count);
+    for (int32_t i = 0; i < count; ++i) off_thr[(size_t)i] = A.take(thr[(size_t)i].size() * 8);
+    std::vector<size_t> off_state((size_t)c->n_chains), off_H((size_t)c->n_chains), off_snap((size_t)c->n_chains),
+        off_given((size_t)c->n_chains, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        const size_t wn = (size_t)((d[i].n + 31) / 32);
+        c->max_words = std::max(c->max_words, (int)wn);
+        c->sk_max_n = std::max(c->sk_max_n, (int)d[i].n);
+        for (int32_t r = 0; r < c->R; ++r) {
+            const size_t ch = (size_t)(i * c->R + r);
+            off_state[ch] = A.take(wn * 4);
+            off_H[ch] = A.take((size_t)d[i].n * 4);
+            off_snap[ch] = A.take(wn * (size_t)c->K * 4);
+            if (d[i].start == SG_START_GIVEN) off_given[ch] = A.take(wn * 4);
+        }
+    }
+    const size_t off_chains = A.take((size_t)c->n_chains * sizeof(SkChain));
+    const size_t off_samples = A.take((size_t)count * sizeof(SkSample));
+    const size_t off_mc = A.take((size_t)c->n_chains * sizeof(MeasureChain));
+    c->n_pairs = count * c->R * (c->R - 1) / 2;
+    const size_t off_pairs = A.take((size_t)std::max(1, c->n_pairs) * 8);
+    const size_t off_bond = A.take((size_t)c->n_chains * c->K * 8);
+    const size_t off_ovl = A.take((size_t)std::max(1, c->n_pairs) * c->K * 8);
+    const size_t off_gram = A.take((size_t)c->n_chains * c->K * c->K * 8);
+    const size_t off_acc = A.take((size_t)c->n_chains * 8);
+    const size_t off_err = A.take(8);
+    c->arena_bytes = A.size;
+    c->arena = c->dev_alloc(A.size);
+
+    // couplings: generated on the host in parallel, or copied
+    parallel_for(jrep.size(), [&](size_t j) {
+        const sg_sk_desc& r = d[jrep[j]];
+        const int64_t n = r.n;
+        if (r.J) {
+            hip_check(hipMemcpy(c->at<void>(off_J[j]), r.J, (size_t)(n * n), hipMemcpyHostToDevice));
+        } else {
+            std::vector<int8_t> J((size_t)(n * n));
+            sk_generate(n, r.seed, r.graph_id, J.data());
+            hip_check(hipMemcpy(c->at<void>(off_J[j]), J.data(), J.size(), hipMemcpyHostToDevice));
+        }
+    });
+    for (int32_t i = 0; i < count; ++i)
+        hip_check(hipMemcpy(c->at<void>(off_thr[(size_t)i]), thr[(size_t)i].data(), thr[(size_t)i].size() * 8,
+                            hipMemcpyHostToDevice));
+
+    c->sk.resize((size_t)c->n_chains);
+    c->sks.resize((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        c->sks[(size_t)i] = SkSample{c->at<int8_t>(off_J[(size_t)jslot[(size_t)i]]), (int32_t)d[i].n, c->R,
+                                     i * c->R, 0};
+        for (int32_t r = 0; r < c->R; ++r) {
+            const size_t ch = (size_t)(i * c->R + r);
+            SkChain S;
+            std::memset(&S, 0, sizeof(S));
+            S.J = c->at<int8_t>(off_J[(size_t)jslot[(size_t)i]]);
+            S.state = c->at<uint32_t>(off_state[ch]);
+            S.H = c->at<int32_t>(off_H[ch]);
+            S.snap = c->at<uint32_t>(off_snap[ch]);
+            S.bond = c->at<long long>(off_bond) + ch * (size_t)c->K;
+            S.accepted = c->at<unsigned long long>(off_acc) + ch;
+            S.thr = c->at<uint64_t>(off_thr[(size_t)i]);
+            S.seed = d[i].seed;
+            S.inst = d[i].instance_id;
+            S.rep = (uint32_t)r;
+            S.n = (int32_t)d[i].n;
+            S.words_n = (int32_t)((d[i].n + 31) / 32);
+            S.thr_len = (int32_t)thr[(size_t)i].size();
+            S.init_mode = d[i].start;
+            S.sample = i;
+            if (d[i].start == SG_START_GIVEN) {
+                const auto bits = pack_given(d[i].s0 + (int64_t)r * d[i].n, d[i].n, nullptr);
+                hip_check(hipMemcpy(c->at<void>(off_given[ch]), bits.data(), bits.size() * 4, hipMemcpyHostToDevice));
+                S.given = c->at<uint32_t>(off_given[ch]);
+            }
+            c->sk[ch] = S;
+        }
+    }
+    std::vector<MeasureChain> mc((size_t)c->n_chains);
+    for (int32_t ch = 0; ch < c->n_chains; ++ch)
+        mc[(size_t)ch] = MeasureChain{c->sk[(size_t)ch].snap, c->sk[(size_t)ch].words_n, c->sk[(size_t)ch].n};
+    std::vector<int32_t> pairs;
+    for (int32_t i = 0; i < count; ++i)
+        for (int32_t a = 0; a < c->R; ++a)
+            for (int32_t b = a + 1; b < c->R; ++b) {
+                pairs.push_back(i * c->R + a);
+                pairs.push_back(i * c->R + b);
+            }
+    c->sk_d = c->at<SkChain>(off_chains);
+    c->sks_d = c->at<SkSample>(off_samples);
+    c->mc_d = c->at<MeasureChain>(off_mc);
+    c->pairs_d = c->at<int32_t>(off_pairs);
+    c->bond_d = c->at<long long>(off_bond);
+    c->overlap_d = c->at<long long>(off_ovl);
+    c->gram_d = c->at<long long>(off_gram);
+    c->acc_d = c->at<unsigned long long>(off_acc);
+    c->err_d = c->at<int>(off_err);
+    hip_check(hipMemcpy(c->sk_d, c->sk.data(), c->sk.size() * sizeof(SkChain), hipMemcpyHostToDevice));
+    hip_check(hipMemcpy(c->sks_d, c->sks.data(), c->sks.size() * sizeof(SkSample), hipMemcpyHostToDevice));
+    hip_check(hipMemcpy(c->mc_d, mc.data(), mc.size() * sizeof(MeasureChain), hipMemcpyHostToDevice));
+    if (!pairs.empty())
+        hip_check(hipMemcpy(c->pairs_d, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
+    hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
+    hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
+    hip_check(zero_i64((long long*)c->err_d, 1, nullptr));
+    c->sk_threads = o && o->threads_per_unit ? o->threads_per_unit : 256;
+    c->sk_lds = sk_lds_bytes(c->sk_max_n);
+    hip_check(sk_init(c->sk_d, c->n_chains, 256, nullptr));
+    hip_check(sk_recompute(c->sks_d, count, c->sk_d, c->sk_max_n, 0, c->err_d, nullptr));
+    hip_check(sk_bond_t0(c->sk_d, c->n_chains, nullptr));
+    hip_check(hipDeviceSynchronize());
+}
+
+template <class F>
+sg_status guarded(F&& f)
+{
+    try {
+        f();
+        return SG_OK;
+    } catch (const Fail& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return SG_ENOMEM;
+    } catch (...) {
+        return SG_EDEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sg_strerror(sg_status s)
+{
+    switch (s) {
+        case SG_OK: return "ok";
+        case SG_EINVAL: return "invalid argument";
+        case SG_ENOMEM: return "out of memory";
+        case SG_EDEVICE: return "HIP device error or no gfx950 device";
+        case SG_ESTATE: return "invalid state";
+        case SG_EPARITY: return "SK incremental fields disagree with the exact recompute";
+        case SG_ENOTSUP: return "request outside supported limits";
+        default: return "unknown status";
+    }
+}
+
+sg_status sg_create_vb(const sg_vb_desc* d, int32_t count, const sg_opts* o, sg_ctx** out)
+{
+    if (!out) return SG_EINVAL;
+    *out = nullptr;
+    if (!d || count < 1) return SG_EINVAL;
+    sg_ctx* c = nullptr;
+    sg_status s = guarded([&]() {
+        c = new sg_ctx();
+        create_vb(c, d, count, o);
+    });
+    if (s != SG_OK) {
+        if (c) {
+            (void)hipDeviceSynchronize();
+            c->release();
+            delete c;
+        }
+        return s;
+    }
+    *out = c;
+    return SG_OK;
+}
+
+sg_status sg_create_sk(const sg_sk_desc* d, int32_t count, const sg_opts* o, sg_ctx** out)
+{
+    if (!out) return SG_EINVAL;
+    *out = nullptr;
+    if (!d || count < 1) return SG_EINVAL;
+    sg_ctx* c = nullptr;
+    sg_status s = guarded([&]() {
+        c = new sg_ctx();
+        create_sk(c, d, count, o);
+    });
+    if (s != SG_OK) {
+        if (c) {
+            (void)hipDeviceSynchronize();
+            c->release();
+            delete c;
+        }
+        return s;
+    }
+    *out = c;
+    return SG_OK;
+}
+
+sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream)
+{
+    if (!c || n_sweeps < 0) return SG_EINVAL;
+    if (c->t_done + n_sweeps >= ((int64_t)1 << 32)) return SG_EINVAL;
+    return guarded([&]() {
+        hip_check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        c->last_stream = s;
+        if (c->kind == 0) {
+            const int64_t cap = std::max<int64_t>(
+                1, std::min<int64_t>(4096, ((int64_t)1 << 36) / std::max<int64_t>(1, c->updates_per_sweep)));
+            int64_t left = n_sweeps;
+            while (left > 0) {
+                const int64_t chunk = std::min(left, cap);
+                hip_check(vb_sweep(c->units_d, (int)c->units.size(), c->vb_threads, c->vb_lds, c->t_done,
+                                   (int32_t)chunk, c->t_max, s));
+                c->t_done += chunk;
+                left -= chunk;
+            }
+        } else {
+            int64_t left = n_sweeps;
+            while (left > 0) {
+                const int64_t to_check = c->period - (c->t_done % c->period);
+                const int64_t chunk = std::min(left, to_check);
+                hip_check(sk_sweep(c->sk_d, c->n_chains, c->sk_threads, c->sk_lds, c->t_done, (int32_t)chunk,
+                                   c->t_max, s));
+                c->t_done += chunk;
+                left -= chunk;
+                if (c->t_done % c->period == 0)
+                    hip_check(sk_recompute(c->sks_d, c->count, c->sk_d, c->sk_max_n, 1, c->err_d, s));
+            }
+        }
+    });
+}
+
+sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
+{
+    if (!c || !out) return SG_EINVAL;
+    int err_flag = 0;
+    sg_status st = guarded([&]() {
+        hip_check(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)stream;
+        const int32_t kd = c->k_done();
+        const int32_t K = c->K, R = c->R;
+        out->count = c->count;
+        out->n_replicas = R;
+        out->k_cap = K;
+        out->k_done = kd;
+        out->t_done = c->t_done;
+        if (flags & SG_MEASURE_OBS) {
+            if (c->kind == 0)
+                hip_check(vb_bond(c->units_d, (int)c->units.size(), kd, c->bond_d, c->unit_chain_ids_d, K,
+                                  std::min(1024, c->vb_threads), c->bond_lds, s));
+            hip_check(measure_overlap(c->mc_d, c->pairs_d, c->n_pairs, kd, K, c->overlap_d, s));
+            hip_check(zero_i64(c->gram_d, (size_t)c->n_chains * K * K, s));
+            hip_check(measure_gram(c->mc_d, c->n_chains, kd, K, c->max_words, c->gram_d, s));
+            std::vector<long long> bond((size_t)c->n_chains * K), ovl((size_t)std::max(1, c->n_pairs) * K),
+                gram((size_t)c->n_chains * K * K);
+            std::vector<unsigned long long> acc((size_t)c->n_chains);
+            hip_check(hipMemcpyAsync(bond.data(), c->bond_d, bond.size() * 8, hipMemcpyDeviceToHost, s));
+            if (c->n_pairs)
+                hip_check(hipMemcpyAsync(ovl.data(), c->overlap_d, (size_t)c->n_pairs * K * 8, hipMemcpyDeviceToHost, s));
+            hip_check(hipMemcpyAsync(gram.data(), c->gram_d, gram.size() * 8, hipMemcpyDeviceToHost, s));
+            hip_check(hipMemcpyAsync(acc.data(), c->acc_d, acc.size() * 8, hipMemcpyDeviceToHost, s));
+            if (c->kind == 1)
+                hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+            hip_check(hipStreamSynchronize(s));
+            if (out->times)
+                for (int32_t k = 0; k < K; ++k) out->times[k] = c->times[(size_t)k];
+            if (out->bond)
+                for (size_t i = 0; i < bond.size(); ++i)
+                    out->bond[i] = (int64_t)i % K < kd ? (int64_t)bond[i] : 0;
+            if (out->overlap && c->n_pairs)
+                for (size_t i = 0; i < (size_t)c->n_pairs * K; ++i)
+                    out->overlap[i] = (int64_t)i % K < kd ? (int64_t)ovl[i] : 0;
+            if (out->gram)
+                for (size_t i = 0; i < gram.size(); ++i) out->gram[i] = (int64_t)gram[i];
+            if (out->accepted)
+                for (size_t i = 0; i < acc.size(); ++i) out->accepted[i] = (int64_t)acc[i];
+        }
+        if ((flags & SG_MEASURE_SPINS) && out->spins) {
+            hip_check(hipStreamSynchronize(s));
+            int64_t base = 0;
+            std::vector<int64_t> inst_base((size_t)c->count);
+            for (int32_t i = 0; i < c->count; ++i) {
+                inst_base[(size_t)i] = base;
+                base += (int64_t)R * c->n_of[(size_t)i];
+            }
+            if (c->kind == 0) {
+                std::vector<std::vector<uint32_t>> st(c->units.size());
+                for (size_t u = 0; u < c->units.size(); ++u) {
+                    st[u].resize((size_t)c->units[u].state_words);
+                    hip_check(hipMemcpy(st[u].data(), c->units[u].state, st[u].size() * 4, hipMemcpyDeviceToHost));
+                }
+                for (int32_t ch = 0; ch < c->n_chains; ++ch) {
+                    const int32_t u = c->chain_loc[(size_t)ch].first, k = c->chain_loc[(size_t)ch].second;
+                    const VbUnit& U = c->units[(size_t)u];
+                    const int32_t i = ch / R, r = ch % R;
+                    const auto& order = c->order_of_group[(size_t)c->group_of_inst[(size_t)i]];
+                    int8_t* dst = out->spins + inst_base[(size_t)i] + (int64_t)r * U.n;
+                    for (int64_t p = 0; p < U.n; ++p) {
+                        const uint64_t b = (uint64_t)p * (uint64_t)U.rpad + (uint64_t)k;
+                        const uint32_t bit = (st[(size_t)u][(size_t)(b >> 5)] >> (b & 31u)) & 1u;
+                        dst[order[(size_t)p]] = bit ? (int8_t)-1 : (int8_t)1;
+                    }
+                }
+            } else {
+                for (int32_t ch = 0; ch < c->n_chains; ++ch) {
+                    const SkChain& S = c->sk[(size_t)ch];
+                    std::vector<uint32_t> st((size_t)S.words_n);
+                    hip_check(hipMemcpy(st.data(), S.state, st.size() * 4, hipMemcpyDeviceToHost));
+                    const int32_t i = ch / R, r = ch % R;
+                    int8_t* dst = out->spins + inst_base[(size_t)i] + (int64_t)r * S.n;
+                    for (int64_t p = 0; p < S.n; ++p)
+                        dst[p] = ((st[(size_t)(p >> 5)] >> (p & 31)) & 1u) ? (int8_t)-1 : (int8_t)1;
+                }
+            }
+        }
+    });
+    if (st != SG_OK) return st;
+    return err_flag ? SG_EPARITY : SG_OK;
+}
+
+void sg_free(sg_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+    (void)hipDeviceSynchronize();
+    c->release();
+    delete c;
+}
+
+sg_status sg_vb_inspect(const sg_vb_desc* d, sg_vb_tables* out)
+{
+    if (!d || !out) return SG_EINVAL;
+    return guarded([&]() {
+        check_vb_desc(*d);
+        VbGraph g;
+        build_vb_graph(*d, g);
+        const size_t m = g.eu.size();
+        out->n_edges = (int64_t)m;
+        out->n_colours = g.ncls;
+        out->max_degree = g.max_degree;
+        if (out->edges)
+            for (size_t e = 0; e < m; ++e) {
+                out->edges[2 * e] = g.eu[e];
+                out->edges[2 * e + 1] = g.ev[e];
+            }
+        if (out->J) std::memcpy(out->J, g.J.data(), m);
+        if (out->colour) std::memcpy(out->colour, g.colour.data(), g.colour.size() * 4);
+        if (out->order) std::memcpy(out->order, g.order.data(), g.order.size() * 4);
+        if (out->row_start) std::memcpy(out->row_start, g.row.data(), g.row.size() * 4);
+        if (out->entries) std::memcpy(out->entries, g.ent.data(), g.ent.size() * 4);
+        if (out->thr)
+            for (int32_t x = 0; x < kVbXMax; ++x) out->thr[x] = x == 0 ? (uint64_t)1 << 32 : threshold(d->T, 1.0, x);
+    });
+}
+
+sg_status sg_sk_inspect(const sg_sk_desc* d, int8_t* J, uint64_t* thr)
+{
+    if (!d) return SG_EINVAL;
+    return guarded([&]() {
+        check_sk_desc(*d);
+        const int64_t n = d->n;
+        if (J) {
+            if (d->J) std::memcpy(J, d->J, (size_t)(n * n));
+            else sk_generate(n, d->seed, d->graph_id, J);
+        }
+        if (thr) {
+            const double s = 1.0 / std::sqrt((double)n);
+            thr[0] = (uint64_t)1 << 32;
+            for (int64_t x = 1; x < n; ++x) thr[x] = threshold(d->T, s, x);
+        }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal device-side descriptors and kernel launchers shared by the host
+// runtime (sg_host.cpp) and the HIP kernels (sg_vb.hip, sg_sk.hip,
+// sg_measure.hip).  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+constexpr int kVbMaxChains = 8;    // chains per VB work unit
+constexpr int kVbXMax = 64;        // threshold table length (max degree 63)
+constexpr int kMaxGrid = 32;       // grid times {0} U {2^k <= t_max}, t_max < 2^31
+constexpr int kSkTile = 64;        // SK decision block (one wavefront)
+constexpr int kSkThrLds = 1024;    // SK threshold entries cached in LDS
+
+// One VB work unit = one workgroup: a graph in sweep (colour) order and up to
+// eight chains that share it.  The chains' spins live in LDS during a launch,
+// vertex-major: position p holds `rpad` bits, bit c belongs to chain c.
+struct VbUnit {
+    const int32_t* row;        // [n+1] adjacency row starts, sweep order
+    const uint32_t* ent;       // [2m] neighbour position | (J < 0) << 31
+    const int32_t* cls;        // [ncls+1] first position of each colour class
+    uint32_t* state;           // [state_words] packed spins between launches
+    uint32_t* snap[kVbMaxChains];       // per chain: [K][words_n] position-order bits
+    unsigned long long* accepted[kVbMaxChains];
+    uint64_t seed[kVbMaxChains];
+    uint32_t inst[kVbMaxChains];
+    uint32_t rep[kVbMaxChains];
+    uint32_t thr_hi[kVbMaxChains][kVbXMax];   // threshold >> 16 (0..65536)
+    uint32_t thr_lo[kVbMaxChains][kVbXMax];   // threshold & 0xffff
+    int32_t n;
+    int32_t ncls;
+    int32_t nch;
+    int32_t rpad;              // bits per position: 1, 2, 4 or 8 (>= nch)
+    int32_t state_words;       // ceil(n * rpad / 32)
+    int32_t words_n;           // ceil(n / 32)
+    int32_t init_mode[kVbMaxChains];   // SG_START_* for the init kernel
+    const uint32_t* given[kVbMaxChains];   // position-order bits when GIVEN
+};
+
+// One SK chain (a replica of an instance).
+struct SkChain {
+    const int8_t* J;           // [n][n]
+    uint32_t* state;           // [words_n] position-order bits (1 = spin -1)
+    int32_t* H;                // [n] local fields between launches
+    uint32_t* snap;            // [K][words_n]
+    long long* bond;           // [K]
+    unsigned long long* accepted;
+    const uint64_t* thr;       // [thr_len] thresholds (uint64), x < thr_len
+    uint64_t seed;
+    uint32_t inst;
+    uint32_t rep;
+    int32_t n;
+    int32_t words_n;
+    int32_t thr_len;           // thr[x] == 0 for x >= thr_len
+    int32_t init_mode;
+    const uint32_t* given;     // position-order bits when GIVEN
+    int32_t sample;            // index of the instance in the context
+    int32_t pad_;
+};
+
+// SK instance (sample) for the exact field recompute: all its chains.
+struct SkSample {
+    const int8_t* J;
+    int32_t n;
+    int32_t nch;
+    int32_t chain0;            // index of its first chain in the chain array
+    int32_t pad_;
+};
+
+struct MeasureChain {
+    const uint32_t* snap;      // [K][words_n]
+    int32_t words_n;
+    int32_t n;
+};
+
+// ---- launchers (return hipError_t) ----
+hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t lds_bytes, hipStream_t s);
+hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, int64_t t0,
+                    int32_t n_sweeps, int64_t t_max, hipStream_t s);
+size_t vb_lds_bytes(int32_t n, int32_t rpad);
+
+hipError_t sk_init(const SkChain* chains, int n_chains, int threads, hipStream_t s);
+hipError_t sk_recompute(const SkSample* samples, int n_samples, const SkChain* chains,
+                        int max_n, int check, int* err_flag, hipStream_t s);
+hipError_t sk_bond_t0(const SkChain* chains, int n_chains, hipStream_t s);
+hipError_t sk_sweep(const SkChain* chains, int n_chains, int threads, size_t lds_bytes, int64_t t0,
+                    int32_t n_sweeps, int64_t t_max, hipStream_t s);
+size_t sk_lds_bytes(int32_t n);
+
+hipError_t vb_bond(const VbUnit* units, int n_units, int k_done, long long* bond_out,
+                   const int32_t* unit_chain_ids, int k_cap, int threads, size_t lds_bytes,
+                   hipStream_t s);
+hipError_t measure_overlap(const MeasureChain* chains, const int32_t* pairs, int n_pairs,
+                           int k_done, int k_cap, long long* out, hipStream_t s);
+hipError_t measure_gram(const MeasureChain* chains, int n_chains, int k_done, int k_cap,
+                        int max_words, long long* out, hipStream_t s);
+hipError_t zero_i64(long long* p, size_t n, hipStream_t s);
+
+}  // namespace sg

@@ -1,0 +1,93 @@
+"""Seeded synthetic workloads (descriptor recipes only).
+
+This module holds no arithmetic of the method: it only lists instance
+descriptors (sizes, temperatures, seeds, ids) for the configurations the
+benchmark and the tests run.  The paper's own graphs, couplings and data are
+not available; these synthetic instances stand in for its workloads (random
+regular bipartite graphs of degree 4 with +-1 couplings and binary SK
+couplings, SI sections on the SK model and on the bipartite graph).
+
+  VB plain    1 instance, 2 replicas, N = 1024, Erdos-Renyi c = 4, J = +-1,
+              T = 0.8, random start, 4096 sweeps, grid {0} U {2^k}, seed 1.
+  VB batched  256 graphs x T in {0.6, 0.8, 1.2} x 2 replicas (1536 chains),
+              N = 65536, c = 4, 2^20 sweeps, seed 2; instance 3 s + tau on
+              graph s.
+  SK          64 samples x 2 replicas, N = 4096, binary couplings, T = 0.5,
+              2^16 sweeps, fields recomputed every 64 sweeps, seed 3.
+  VB uneven   1024 instances, N = floor(2^(10 + 10 U)), T from {0.6, 0.8, 1.0},
+              2 replicas, 2^14 sweeps, seed 4 (U, T index from numpy's
+              default_rng(4)).
+  serving     Poisson arrivals; 70 % VB with N log-uniform in [2^12, 2^20],
+              30 % SK with N log-uniform in [512, 8192]; T ~ U[0.5, 0.9];
+              2^k sweeps, k uniform in {12..16}; seed 5.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+
+from . import VbDesc, SkDesc
+
+VB_PLAIN_SWEEPS = 4096
+VB_BATCHED_SWEEPS = 1 << 20
+SK_SWEEPS = 1 << 16
+VB_UNEVEN_SWEEPS = 1 << 14
+
+
+def vb_plain() -> List[VbDesc]:
+    return [VbDesc(n=1024, T=0.8, seed=1, instance_id=0, graph_id=0, c=4.0, n_replicas=2)]
+
+
+def vb_batched(n_graphs: int = 256, n: int = 65536, temps=(0.6, 0.8, 1.2)) -> List[VbDesc]:
+    out = []
+    for s in range(n_graphs):
+        for tau, T in enumerate(temps):
+            out.append(VbDesc(n=n, T=T, seed=2, instance_id=len(temps) * s + tau, graph_id=s, c=4.0,
+                              n_replicas=2))
+    return out
+
+
+def sk_batch(n_samples: int = 64, n: int = 4096, T: float = 0.5) -> List[SkDesc]:
+    return [SkDesc(n=n, T=T, seed=3, instance_id=s, graph_id=s, n_replicas=2, recompute_period=64)
+            for s in range(n_samples)]
+
+
+def vb_uneven(count: int = 1024, lo: int = 10, hi: int = 20, temps=(0.6, 0.8, 1.0)) -> List[VbDesc]:
+    rng = np.random.default_rng(4)
+    U = rng.random(count)
+    V = rng.random(count)
+    out = []
+    for i in range(count):
+        n = int(np.floor(2.0 ** (lo + (hi - lo) * U[i])))
+        T = temps[int(np.floor(len(temps) * V[i]))]
+        out.append(VbDesc(n=n, T=T, seed=4, instance_id=i, graph_id=i, c=4.0, n_replicas=2))
+    return out
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float       # seconds after the start
+    kind: str            # "vb" or "sk"
+    n: int
+    T: float
+    sweeps: int
+
+
+def serving_requests(count: int, rate: float, seed: int = 5) -> List[Request]:
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += rng.exponential(1.0 / rate)
+        kind = "vb" if rng.random() < 0.7 else "sk"
+        if kind == "vb":
+            n = int(np.floor(2.0 ** rng.uniform(12, 20)))
+        else:
+            n = int(np.floor(2.0 ** rng.uniform(9, 13)))
+        T = float(rng.uniform(0.5, 0.9))
+        sweeps = 1 << int(rng.integers(12, 17))
+        out.append(Request(rid, t, kind, n, T, sweeps))
+    return out
