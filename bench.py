@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-vb", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -216,6 +218,21 @@ def main():
     from paper_1906_11195_amd import workloads
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        # A plain copy kernel of known size: reads and writes exactly
+        # copy_probe_mib MiB; used to scale the FETCH_SIZE / WRITE_SIZE counters.
+        n = args.copy_probe_mib << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            # evict the source from the caches (L2 and the 256 MB Infinity
+            # Cache) with an unrelated fill before each copy
+            evict = torch.full((512 << 20,), 3, dtype=torch.uint8, device="cuda")
+            del evict
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
+        return
     sg.library()
     vb = run_vb_batched(args, torch, sg, workloads)
     log("VB batched: %.1f updates/ns" % vb["value"])

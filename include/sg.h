@@ -29,9 +29,10 @@
  * Update order (the paper's bipartite parallel update, SI "Simulations of the
  * Bethe Lattice on GPUs", generalised to any graph): the vertices are coloured
  * greedily in vertex order (colour(v) = smallest colour not used by a
- * neighbour u < v); the sweep visits colour class 0, then class 1, ..., each
- * class in increasing vertex id.  "Position" p is the index of a vertex in
- * that visiting order.  SK visits i = 0..N-1 (fixed order, SI SK section),
+ * neighbour u < v); the sweep visits colour class 0, then class 1, ...; inside
+ * a class by decreasing degree, ties by increasing vertex id (the order inside
+ * a class does not change the dynamics' law; it fixes which random number each
+ * spin uses).  "Position" p is the index of a vertex in that visiting order.  SK visits i = 0..N-1 (fixed order, SI SK section),
  * so p = i.
  *
  * Random numbers.  The paper names no generator.  This library uses

@@ -74,7 +74,7 @@ def _load():
         lib.orc_sk_couplings.argtypes = [i64, u64, u32, P]
         lib.orc_greedy_colour.argtypes = [i64, i64, P, P, P]
         lib.orc_greedy_colour.restype = i32
-        lib.orc_sweep_order.argtypes = [i64, P, i32, P]
+        lib.orc_sweep_order.argtypes = [i64, P, i32, P, P]
         lib.orc_thresholds.argtypes = [f64, f64, i32, P]
         lib.orc_grid.argtypes = [i64, P]
         lib.orc_grid.restype = i32
@@ -155,11 +155,18 @@ def greedy_colour(n: int, eu, ev):
     return colour, int(ncol)
 
 
-def sweep_order(colour, ncol: int) -> np.ndarray:
+def sweep_order(colour, ncol: int, deg) -> np.ndarray:
+    """Visiting order: colour classes in order, each by decreasing degree,
+    ties by increasing vertex id."""
     colour = np.ascontiguousarray(colour, dtype=np.int32)
+    deg = np.ascontiguousarray(deg, dtype=np.int32)
     order = np.zeros(len(colour), dtype=np.int32)
-    _load().orc_sweep_order(len(colour), _ptr(colour), ncol, _ptr(order))
+    _load().orc_sweep_order(len(colour), _ptr(colour), ncol, _ptr(deg), _ptr(order))
     return order
+
+
+def degrees(n: int, eu, ev) -> np.ndarray:
+    return np.bincount(np.concatenate([np.asarray(eu), np.asarray(ev)]), minlength=n).astype(np.int32)
 
 
 def thresholds(T: float, de_scale: float, xmax: int) -> np.ndarray:

@@ -265,14 +265,20 @@ int32_t orc_greedy_colour(int64_t n, int64_t m, const int32_t* eu, const int32_t
     return ncol;
 }
 
-/* Sweep order: class 0 in increasing vertex id, then class 1, ...
- * order[p] is the vertex visited at position p. */
-void orc_sweep_order(int64_t n, const int32_t* colour, int32_t ncol, int32_t* order)
+/* Sweep order: class 0, then class 1, ...; inside a class by decreasing
+ * degree, ties by increasing vertex id.  order[p] is the vertex visited at
+ * position p. */
+void orc_sweep_order(int64_t n, const int32_t* colour, int32_t ncol, const int32_t* deg,
+                     int32_t* order)
 {
+    int32_t maxdeg = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (deg[v] > maxdeg) maxdeg = deg[v];
     int64_t p = 0;
     for (int32_t c = 0; c < ncol; ++c)
-        for (int64_t v = 0; v < n; ++v)
-            if (colour[v] == c) order[p++] = (int32_t)v;
+        for (int32_t d = maxdeg; d >= 0; --d)
+            for (int64_t v = 0; v < n; ++v)
+                if (colour[v] == c && deg[v] == d) order[p++] = (int32_t)v;
 }
 
 /* Metropolis acceptance thresholds, thr[x] = floor(2^32 exp(-beta dE)) for
@@ -329,7 +335,10 @@ int orc_vb_run(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const
     int32_t* colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int32_t ncol = orc_greedy_colour(n, m, eu, ev, colour);
-    orc_sweep_order(n, colour, ncol, order);
+    int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    for (int64_t v = 0; v < n; ++v) deg[v] = (int32_t)(g.start[v + 1] - g.start[v]);
+    orc_sweep_order(n, colour, ncol, deg, order);
+    free(deg);
     int64_t maxdeg = 0;
     for (int64_t v = 0; v < n; ++v)
         if (g.start[v + 1] - g.start[v] > maxdeg) maxdeg = g.start[v + 1] - g.start[v];

@@ -132,15 +132,19 @@ void vb_tables(VbGraph& g)
     }
     g.ncls = ncls;
 
-    // positions: class by class, increasing id inside a class (counting sort)
+    // positions: class by class; inside a class by decreasing degree, ties by
+    // increasing id (counting sort on the key (class, max_degree - degree))
+    const int32_t nd = g.max_degree + 1;
+    std::vector<int32_t> bucket((size_t)ncls * nd + 1, 0);
+    auto key = [&](int64_t v) { return (size_t)g.colour[(size_t)v] * nd + (size_t)(g.max_degree - deg[(size_t)v]); };
+    for (int64_t v = 0; v < n; ++v) bucket[key(v) + 1]++;
+    for (size_t b = 0; b + 1 < bucket.size(); ++b) bucket[b + 1] += bucket[b];
     g.cls.assign((size_t)ncls + 1, 0);
-    for (int64_t v = 0; v < n; ++v) g.cls[(size_t)g.colour[(size_t)v] + 1]++;
-    for (int32_t c = 0; c < ncls; ++c) g.cls[(size_t)c + 1] += g.cls[(size_t)c];
-    std::vector<int32_t> next(g.cls.begin(), g.cls.end() - 1);
+    for (int32_t c = 0; c <= ncls; ++c) g.cls[(size_t)c] = bucket[(size_t)c * nd];
     g.order.assign((size_t)n, 0);
     std::vector<int32_t> pos((size_t)n);
     for (int64_t v = 0; v < n; ++v) {
-        const int32_t p = next[(size_t)g.colour[(size_t)v]]++;
+        const int32_t p = bucket[key(v)]++;
         g.order[(size_t)p] = (int32_t)v;
         pos[(size_t)v] = p;
     }
@@ -155,6 +159,37 @@ void vb_tables(VbGraph& g)
                                  (vj[(size_t)a] < 0 ? 0x80000000u : 0u);
     }
     g.row[(size_t)n] = (int32_t)e;
+}
+
+// Cuts every colour class into tiles of at most `threads` lanes (lane i takes
+// position (p0 & ~7) + i).  A streamed tile also holds at most
+// vb_tile_entries(threads) adjacency entries.  Tiles end on a multiple of 8
+// unless they end their class, so that an aligned group of 8 positions never
+// straddles two tiles of one class.
+std::vector<VbTile> vb_tile_plan(const VbGraph& g, int threads, bool resident)
+{
+    std::vector<VbTile> out;
+    const int32_t ecap = vb_tile_entries(threads);
+    for (int32_t k = 0; k < g.ncls; ++k) {
+        const int32_t end = g.cls[(size_t)k + 1];
+        int32_t p = g.cls[(size_t)k];
+        while (p < end) {
+            int32_t q = std::min<int32_t>(end, (p & ~7) + threads);
+            if (!resident && g.row[(size_t)q] - g.row[(size_t)p] > ecap) {
+                int32_t lo = p + 1, hi = q;   // largest q' with at most ecap entries
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) / 2;
+                    if (g.row[(size_t)mid] - g.row[(size_t)p] <= ecap) lo = mid;
+                    else hi = mid - 1;
+                }
+                q = lo & ~7;
+                if (q <= p) q = std::min<int32_t>(end, (p & ~7) + 8);
+            }
+            out.push_back(VbTile{p, q, g.row[(size_t)p], g.row[(size_t)q] - g.row[(size_t)p]});
+            p = q;
+        }
+    }
+    return out;
 }
 
 bool finite_nonneg_T(double T) { return !(T < 0.0) && !std::isnan(T); }
@@ -486,8 +521,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         const int64_t n = graphs[gi].n;
         int32_t per = std::min<int32_t>(want, (int32_t)chains_of[gi].size());
         auto rpad_of = [](int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; };
-        while (per > 1 && vb_lds_bytes((int32_t)n, rpad_of(per)) > lds_cap) --per;
-        if (vb_lds_bytes((int32_t)n, rpad_of(per)) > lds_cap) fail(SG_ENOTSUP);
+        while (per > 1 && vb_lds_bytes((int32_t)n, rpad_of(per), 64) > lds_cap) --per;
+        if (vb_lds_bytes((int32_t)n, rpad_of(per), 64) > lds_cap) fail(SG_ENOTSUP);
         const auto& ch = chains_of[gi];
         for (size_t a = 0; a < ch.size(); a += (size_t)per) {
             UnitPlan u;
@@ -498,13 +533,41 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         }
     }
 
+    // workgroup size: wide enough for the largest colour class, small enough
+    // for every unit's LDS
+    int threads = 64;
+    if (o && o->threads_per_unit) {
+        threads = o->threads_per_unit;
+    } else {
+        int32_t maxcls = 0;
+        for (const auto& g : graphs)
+            for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
+        threads = (int)std::min<int32_t>(1024, std::max<int32_t>(64, (maxcls + 63) / 64 * 64));
+        auto fits = [&](int th) {
+            for (const auto& u : plan)
+                if (vb_lds_bytes((int32_t)graphs[(size_t)u.group].n, u.rpad, th) > lds_cap) return false;
+            return true;
+        };
+        while (threads > 64 && !fits(threads)) threads -= 64;
+    }
+    for (const auto& u : plan)
+        if (vb_lds_bytes((int32_t)graphs[(size_t)u.group].n, u.rpad, threads) > lds_cap) fail(SG_ENOTSUP);
+    std::vector<std::vector<VbTile>> tiles(n_groups);
+    std::vector<int32_t> resident(n_groups);
+    for (size_t gi = 0; gi < n_groups; ++gi) {
+        const VbGraph& g = graphs[gi];
+        resident[gi] = (size_t)(g.n + 1 + (int64_t)g.ent.size()) * 4 <= vb_area_bytes(threads);
+        tiles[gi] = vb_tile_plan(g, threads, resident[gi] != 0);
+    }
+
     // device layout
     Arena A;
-    std::vector<size_t> off_row(n_groups), off_ent(n_groups), off_cls(n_groups);
+    std::vector<size_t> off_row(n_groups), off_ent(n_groups), off_cls(n_groups), off_tiles(n_groups);
     for (size_t gi = 0; gi < n_groups; ++gi) {
         off_row[gi] = A.take(graphs[gi].row.size() * 4);
         off_ent[gi] = A.take(std::max<size_t>(1, graphs[gi].ent.size()) * 4);
         off_cls[gi] = A.take(graphs[gi].cls.size() * 4);
+        off_tiles[gi] = A.take(std::max<size_t>(1, tiles[gi].size()) * sizeof(VbTile));
     }
     std::vector<size_t> off_state(plan.size());
     for (size_t u = 0; u < plan.size(); ++u) {
@@ -542,6 +605,9 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         if (!g.ent.empty())
             hip_check(hipMemcpy(c->at<void>(off_ent[gi]), g.ent.data(), g.ent.size() * 4, hipMemcpyHostToDevice));
         hip_check(hipMemcpy(c->at<void>(off_cls[gi]), g.cls.data(), g.cls.size() * 4, hipMemcpyHostToDevice));
+        if (!tiles[gi].empty())
+            hip_check(hipMemcpy(c->at<void>(off_tiles[gi]), tiles[gi].data(), tiles[gi].size() * sizeof(VbTile),
+                                hipMemcpyHostToDevice));
     }
     for (int32_t i = 0; i < count; ++i) {
         if (d[i].start != SG_START_GIVEN) continue;
@@ -556,7 +622,6 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     c->units.resize(plan.size());
     std::vector<int32_t> ids(plan.size() * kVbMaxChains, 0);
     c->chain_loc.resize((size_t)c->n_chains);
-    int max_threads = 64;
     c->updates_per_sweep = 0;
     for (size_t u = 0; u < plan.size(); ++u) {
         const VbGraph& g = graphs[(size_t)plan[u].group];
@@ -565,6 +630,10 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         U.row = c->at<int32_t>(off_row[(size_t)plan[u].group]);
         U.ent = c->at<uint32_t>(off_ent[(size_t)plan[u].group]);
         U.cls = c->at<int32_t>(off_cls[(size_t)plan[u].group]);
+        U.tiles = c->at<VbTile>(off_tiles[(size_t)plan[u].group]);
+        U.ntiles = (int32_t)tiles[(size_t)plan[u].group].size();
+        U.resident = resident[(size_t)plan[u].group];
+        U.m2 = (int32_t)g.ent.size();
         U.state = c->at<uint32_t>(off_state[u]);
         U.n = (int32_t)g.n;
         U.ncls = g.ncls;
@@ -591,13 +660,11 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
             c->chain_loc[(size_t)ch] = {(int32_t)u, k};
         }
         c->units[u] = U;
-        const int64_t groups8 = (g.n + 7) / 8;
-        max_threads = std::max<int>(max_threads, (int)std::min<int64_t>(1024, ((groups8 + 63) / 64) * 64));
-        c->vb_lds = std::max(c->vb_lds, vb_lds_bytes(U.n, U.rpad));
+        c->vb_lds = std::max(c->vb_lds, vb_lds_bytes(U.n, U.rpad, threads));
         c->bond_lds = std::max(c->bond_lds, (size_t)(((U.nch * U.words_n + 1) & ~1) * 4 + kVbMaxChains * 8));
         c->updates_per_sweep += g.n * U.nch;
     }
-    c->vb_threads = o && o->threads_per_unit ? o->threads_per_unit : max_threads;
+    c->vb_threads = threads;
     c->order_of_group.resize(n_groups);
     for (size_t gi = 0; gi < n_groups; ++gi) c->order_of_group[gi] = std::move(graphs[gi].order);
 

@@ -16,10 +16,23 @@ constexpr int kSkThrLds = 1024;    // SK threshold entries cached in LDS
 // One VB work unit = one workgroup: a graph in sweep (colour) order and up to
 // eight chains that share it.  The chains' spins live in LDS during a launch,
 // vertex-major: position p holds `rpad` bits, bit c belongs to chain c.
+// A tile is a run of positions [p0, p1) of one colour class whose adjacency
+// (row starts p0..p1 and entries e0 .. e0+ne) is staged in LDS at once.
+// Lane i of the workgroup takes position (p0 & ~7) + i; p1 <= (p0 & ~7) +
+// threads; a tile ends on a multiple of 8 unless it ends its class.
+struct VbTile {
+    int32_t p0, p1, e0, ne;
+};
+
 struct VbUnit {
     const int32_t* row;        // [n+1] adjacency row starts, sweep order
     const uint32_t* ent;       // [2m] neighbour position | (J < 0) << 31
     const int32_t* cls;        // [ncls+1] first position of each colour class
+    const VbTile* tiles;       // [ntiles] one sweep, class by class
+    int32_t ntiles;
+    int32_t resident;          // 1: whole adjacency kept in LDS for the launch
+    int32_t m2;                // 2m entries
+    int32_t pad0_;
     uint32_t* state;           // [state_words] packed spins between launches
     uint32_t* snap[kVbMaxChains];       // per chain: [K][words_n] position-order bits
     unsigned long long* accepted[kVbMaxChains];
@@ -78,7 +91,11 @@ struct MeasureChain {
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t lds_bytes, hipStream_t s);
 hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, int64_t t0,
                     int32_t n_sweeps, int64_t t_max, hipStream_t s);
-size_t vb_lds_bytes(int32_t n, int32_t rpad);
+// Entries a streamed tile may hold, and the LDS a unit needs, for a launch
+// with `threads` lanes per workgroup.
+int32_t vb_tile_entries(int threads);
+size_t vb_area_bytes(int threads);
+size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads);
 
 hipError_t sk_init(const SkChain* chains, int n_chains, int threads, hipStream_t s);
 hipError_t sk_recompute(const SkSample* samples, int n_samples, const SkChain* chains,

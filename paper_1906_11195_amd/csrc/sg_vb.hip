@@ -5,96 +5,155 @@
 // generalised; SI "Simulations of the Bethe Lattice on GPUs") and up to eight
 // chains that share it.  The chains' spins stay in LDS for the whole launch,
 // packed vertex-major (rpad bits per position, bit c = chain c), so that one
-// LDS read of a neighbour returns its spin in every chain.  The adjacency
-// (row starts + packed entries) is streamed from HBM once per sweep for all
-// chains of the unit.
+// LDS read of a neighbour returns its spin in every chain.
 //
-// A sweep visits colour class 0, 1, ...; inside a class every position is
-// independent (no two positions of a class are adjacent), so the class is
-// split over the lanes: one lane takes an aligned group of 8 positions, which
-// shares one Philox block per chain for the acceptance draws.  A workgroup
-// barrier separates classes.  Flips are XORed into LDS.
+// A sweep visits colour class 0, 1, ...; inside a class all positions are
+// independent (no two are adjacent).  The classes are cut into tiles of at
+// most `threads` positions; lane i of the workgroup updates position
+// (p0 & ~7) + i of the tile, for every chain of the unit.  The tile's
+// adjacency (row starts and packed entries) sits in LDS: either the whole
+// graph is resident for the launch, or tiles are streamed from HBM with
+// coalesced loads issued one tile ahead (double buffer), so the load of tile
+// k+1 overlaps the updates of tile k.  One workgroup barrier ends each tile.
 //
 // Metropolis rule (Methods; SI bipartite-graph section): with x = s_p h_p the
 // move is accepted if x <= 0, else iff r < thr[x], thr[x] = floor(2^32
-// exp(-2x/T)).  r = (A << 16) | B with A, B half-words of two Philox streams;
-// B is evaluated only when A ties with the threshold's high half.
+// exp(-2x/T)).  r = (A << 16) | B with A, B half-words of two Philox streams.
+// The eight lanes of an aligned group of 8 positions share one Philox block
+// per chain: lane j computes the block of chain j and the group exchanges the
+// half-words through LDS.  B is computed only when A ties with the high half
+// of the threshold (probability 2^-16).
 #include "sg_internal.h"
 #include "sg_philox.h"
 
 namespace sg {
 namespace {
 
-template <int RPAD>
-__device__ __forceinline__ void vb_group(const VbUnit* __restrict__ up, uint32_t* __restrict__ sp,
-                                         const uint32_t* __restrict__ thi,
-                                         const uint32_t* __restrict__ tlo, int32_t g, int32_t lo,
-                                         int32_t hi, uint32_t t, int32_t nch, uint32_t* acc)
-{
-    const int32_t* __restrict__ row = up->row;
-    const uint32_t* __restrict__ ent = up->ent;
-    const int32_t pb = g << 3;
+constexpr int kEntPerLane = 6;   // streamed-tile entries per lane
 
-    U4 A[RPAD];
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct VbLds {
+    uint32_t* sp;                 // spins, vertex-major
+    uint32_t* thi;                // [8][64]
+    uint32_t* tlo;                // [8][64]
+    unsigned long long* accs;     // [8]
+    uint4* xch;                   // [threads] Philox blocks
+    int32_t* area;                // adjacency: resident graph or two tile buffers
+};
+
+__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr)
+{
+    VbLds L;
+    L.sp = smem;
+    L.thi = smem + ((sw + 3) & ~3);
+    L.tlo = L.thi + kVbMaxChains * kVbXMax;
+    L.accs = (unsigned long long*)(L.tlo + kVbMaxChains * kVbXMax);
+    L.xch = (uint4*)(L.accs + kVbMaxChains);
+    L.area = (int32_t*)(L.xch + nthr);
+    return L;
+}
+
+struct Prefetch {
+    int32_t r[2];
+    uint32_t e[kEntPerLane];
+};
+
+__device__ __forceinline__ void tile_fetch(const VbUnit* __restrict__ up, const VbTile& T, int tid,
+                                           int nthr, Prefetch& pf)
+{
+    const int32_t nr = T.p1 - T.p0 + 1;
+    pf.r[0] = tid < nr ? up->row[T.p0 + tid] : 0;
+    pf.r[1] = tid + nthr < nr ? up->row[T.p0 + tid + nthr] : 0;
+#pragma unroll
+    for (int k = 0; k < kEntPerLane; ++k) {
+        const int32_t idx = tid + k * nthr;
+        pf.e[k] = idx < T.ne ? up->ent[T.e0 + idx] : 0u;
+    }
+}
+
+__device__ __forceinline__ void tile_store(int32_t* buf, const VbTile& T, int tid, int nthr,
+                                           const Prefetch& pf)
+{
+    const int32_t nr = T.p1 - T.p0 + 1;
+    if (tid < nr) buf[tid] = pf.r[0];
+    if (tid + nthr < nr) buf[tid + nthr] = pf.r[1];
+    uint32_t* eb = (uint32_t*)(buf + nthr + 8);
+#pragma unroll
+    for (int k = 0; k < kEntPerLane; ++k) {
+        const int32_t idx = tid + k * nthr;
+        if (idx < T.ne) eb[idx] = pf.e[k];
+    }
+}
+
+// Updates the positions of one tile for every chain of the unit.
+template <int RPAD>
+__device__ __forceinline__ void vb_tile(const VbUnit* __restrict__ up, const VbLds& L,
+                                        const VbTile& T, const int32_t* __restrict__ rows,
+                                        const uint32_t* __restrict__ ents, int32_t rbase,
+                                        int32_t ebase, uint32_t t, int32_t nch, uint64_t my_seed,
+                                        uint32_t my_rep, uint32_t my_inst, uint32_t* acc)
+{
+    const int tid = threadIdx.x;
+    const int32_t q = (T.p0 & ~7) + tid;
+    const int cc = tid & 7;
+
+    // Philox block of chain cc for the group of q (shared by the 8 lanes).
+    U4 A = U4{0, 0, 0, 0};
+    if (cc < nch) A = philox_stream(my_seed, (uint32_t)q >> 3, t, kDomSweepHi, my_rep, my_inst);
+    L.xch[tid] = make_uint4(A.x, A.y, A.z, A.w);
+    wave_sync();
+    if (q < T.p0 || q >= T.p1) return;
+
+    const int32_t r0 = rows[q - rbase];
+    const int32_t r1 = rows[q - rbase + 1];
+    const uint32_t ob = (uint32_t)q * RPAD;
+    const uint32_t own = L.sp[ob >> 5] >> (ob & 31u);
+    uint32_t c0 = 0, c1 = 0;
+    for (int32_t e = r0; e < r1; ++e) {
+        const uint32_t en = ents[e - ebase];
+        const uint32_t qb = (en & 0x7fffffffu) * RPAD;
+        // bit c of f is 1 iff the bond (q, neighbour) is unsatisfied in chain c
+        const uint32_t f = (L.sp[qb >> 5] >> (qb & 31u)) ^ own ^ (uint32_t)((int32_t)en >> 31);
+        if (RPAD == 1) {
+            c0 += f & 1u;
+        } else {
+            // one byte counter per chain (degree <= 63)
+            c0 += ((f & 0xFu) * 0x00204081u) & 0x01010101u;
+            if (RPAD == 8) c1 += (((f >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
+        }
+    }
+    const int32_t deg = r1 - r0;
+    const uint32_t* gx = (const uint32_t*)(L.xch + (tid & ~7));
+    const uint32_t hsel = (uint32_t)tid & 7u;
+    uint32_t fl = 0;
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) {
-        if (c < nch)
-            A[c] = philox_stream(up->seed[c], (uint32_t)g, t, kDomSweepHi, up->rep[c], up->inst[c]);
-        else
-            A[c] = U4{0, 0, 0, 0};
-    }
-
-    uint64_t fl = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int32_t p = pb + j;
-        if (p < lo || p >= hi) continue;
-        const int32_t e0 = row[p];
-        const int32_t e1 = row[p + 1];
-        const uint32_t ob = (uint32_t)p * RPAD;
-        const uint32_t own = sp[ob >> 5] >> (ob & 31u);
-        uint32_t cnt[RPAD];
-#pragma unroll
-        for (int c = 0; c < RPAD; ++c) cnt[c] = 0;
-        for (int32_t e = e0; e < e1; ++e) {
-            const uint32_t en = ent[e];
-            const uint32_t qb = (en & 0x7fffffffu) * RPAD;
-            // bit c of f is 1 iff the bond (p, q) is unsatisfied in chain c
-            const uint32_t f = (sp[qb >> 5] >> (qb & 31u)) ^ own ^ (uint32_t)((int32_t)en >> 31);
-#pragma unroll
-            for (int c = 0; c < RPAD; ++c) cnt[c] += (f >> c) & 1u;
-        }
-        const int32_t deg = e1 - e0;
-#pragma unroll
-        for (int c = 0; c < RPAD; ++c) {
-            if (c >= nch) break;
-            const int32_t x = deg - 2 * (int32_t)cnt[c];   // x = s_p h_p
-            bool flip = x <= 0;
-            if (!flip) {
-                const uint32_t th = thi[c * kVbXMax + x];
-                const uint32_t rh = half_word(A[c], (uint32_t)j);
-                flip = rh < th;
-                if (rh == th) {
-                    const U4 B = philox_stream(up->seed[c], (uint32_t)g, t, kDomSweepLo, up->rep[c],
-                                               up->inst[c]);
-                    flip = half_word(B, (uint32_t)j) < tlo[c * kVbXMax + x];
-                }
-            }
-            if (flip) {
-                fl |= 1ull << (j * RPAD + c);
-                acc[c] += 1;
+        if (c >= nch) break;
+        const uint32_t cnt = RPAD == 1 ? c0 : (((c < 4) ? (c0 >> (8 * c)) : (c1 >> (8 * (c - 4)))) & 0xFFu);
+        const int32_t x = deg - 2 * (int32_t)cnt;   // x = s_q h_q
+        bool flip = x <= 0;
+        if (!flip) {
+            const uint32_t th = L.thi[c * kVbXMax + x];
+            const uint32_t rh = (gx[4 * c + (hsel >> 1)] >> (16u * (hsel & 1u))) & 0xffffu;
+            flip = rh < th;
+            if (rh == th) {
+                const U4 B = philox_stream(up->seed[c], (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c],
+                                           up->inst[c]);
+                flip = half_word(B, hsel) < L.tlo[c * kVbXMax + x];
             }
         }
-    }
-    if (fl) {
-        const uint32_t gb = (uint32_t)pb * RPAD;
-        if (RPAD == 8) {
-            if ((uint32_t)fl) atomicXor(&sp[gb >> 5], (uint32_t)fl);
-            if ((uint32_t)(fl >> 32)) atomicXor(&sp[(gb >> 5) + 1], (uint32_t)(fl >> 32));
-        } else {
-            atomicXor(&sp[gb >> 5], (uint32_t)fl << (gb & 31u));
+        if (flip) {
+            fl |= 1u << c;
+            acc[c] += 1;
         }
     }
+    if (fl) atomicXor(&L.sp[ob >> 5], fl << (ob & 31u));
 }
 
 template <int RPAD>
@@ -119,54 +178,85 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
                        int64_t t_max)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int32_t sw = up->state_words;
-    uint32_t* sp = smem;
-    uint32_t* thi = smem + ((sw + 3) & ~3);
-    uint32_t* tlo = thi + kVbMaxChains * kVbXMax;
-    unsigned long long* accs = (unsigned long long*)(tlo + kVbMaxChains * kVbXMax);
+    const int32_t sw = up->state_words, n = up->n, nch = up->nch;
+    const VbLds L = vb_carve(smem, sw, nthr);
+    const bool res = up->resident != 0;
 
-    for (int32_t w = tid; w < sw; w += nthr) sp[w] = up->state[w];
+    for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = up->state[w];
     for (int i = tid; i < kVbMaxChains * kVbXMax; i += nthr) {
-        thi[i] = (&up->thr_hi[0][0])[i];
-        tlo[i] = (&up->thr_lo[0][0])[i];
+        L.thi[i] = (&up->thr_hi[0][0])[i];
+        L.tlo[i] = (&up->thr_lo[0][0])[i];
     }
-    if (tid < kVbMaxChains) accs[tid] = 0;
+    if (tid < kVbMaxChains) L.accs[tid] = 0;
+    if (res) {
+        for (int32_t i = tid; i <= n; i += nthr) L.area[i] = up->row[i];
+        uint32_t* re = (uint32_t*)(L.area + n + 1);
+        for (int32_t i = tid; i < up->m2; i += nthr) re[i] = up->ent[i];
+    }
+    // chain whose Philox block this lane computes
+    const int cc = tid & 7;
+    const uint64_t my_seed = cc < nch ? up->seed[cc] : 0ull;
+    const uint32_t my_rep = cc < nch ? up->rep[cc] : 0u;
+    const uint32_t my_inst = cc < nch ? up->inst[cc] : 0u;
+
+    const int32_t nt = up->ntiles;
+    const VbTile* __restrict__ tiles = up->tiles;
+    const int64_t total = (int64_t)nsw * nt;
+    const int32_t bufw = nthr + 8 + kEntPerLane * nthr;
+    Prefetch pf;
+    if (!res && total > 0) {
+        const VbTile T0 = tiles[0];
+        tile_fetch(up, T0, tid, nthr, pf);
+        tile_store(L.area, T0, tid, nthr, pf);
+        if (total > 1) tile_fetch(up, tiles[1 % nt], tid, nthr, pf);
+    }
     __syncthreads();
 
-    const int32_t ncls = up->ncls, nch = up->nch;
-    const int32_t* __restrict__ cls = up->cls;
     uint32_t acc[RPAD];
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) acc[c] = 0;
 
-    for (int32_t s = 0; s < nsw; ++s) {
+    int32_t ti = 0, s = 0;
+    for (int64_t it = 0; it < total; ++it) {
         const uint32_t t = (uint32_t)(t0 + s);
-        for (int32_t c = 0; c < ncls; ++c) {
-            const int32_t lo = cls[c], hi = cls[c + 1];
-            const int32_t g1 = (hi + 7) >> 3;
-            for (int32_t g = (lo >> 3) + tid; g < g1; g += nthr)
-                vb_group<RPAD>(up, sp, thi, tlo, g, lo, hi, t, nch, acc);
-            __syncthreads();
+        const VbTile T = tiles[ti];
+        if (res) {
+            vb_tile<RPAD>(up, L, T, L.area, (const uint32_t*)(L.area + n + 1), 0, 0, t, nch, my_seed,
+                          my_rep, my_inst, acc);
+        } else {
+            const int32_t* buf = L.area + (int32_t)(it & 1) * bufw;
+            vb_tile<RPAD>(up, L, T, buf, (const uint32_t*)(buf + nthr + 8), T.p0, T.e0, t, nch,
+                          my_seed, my_rep, my_inst, acc);
+            if (it + 1 < total) {
+                const VbTile Tn = tiles[ti + 1 == nt ? 0 : ti + 1];
+                tile_store(L.area + (int32_t)((it + 1) & 1) * bufw, Tn, tid, nthr, pf);
+            }
         }
-        const int64_t tn = t0 + s + 1;
-        if (tn <= t_max && (tn & (tn - 1)) == 0) {
-            vb_snapshot<RPAD>(up, sp, 1 + (63 - __clzll((unsigned long long)tn)));
-            __syncthreads();
+        __syncthreads();
+        if (!res && it + 2 < total) tile_fetch(up, tiles[(ti + 2) % nt], tid, nthr, pf);
+        if (++ti == nt) {
+            ti = 0;
+            ++s;
+            const int64_t tn = t0 + s;
+            if (tn <= t_max && (tn & (tn - 1)) == 0) {
+                vb_snapshot<RPAD>(up, L.sp, 1 + (63 - __clzll((unsigned long long)tn)));
+                __syncthreads();
+            }
         }
     }
 
-    for (int32_t w = tid; w < sw; w += nthr) up->state[w] = sp[w];
+    for (int32_t w = tid; w < sw; w += nthr) up->state[w] = L.sp[w];
 #pragma unroll
     for (int c = 0; c < RPAD; ++c)
-        if (c < nch && acc[c]) atomicAdd(&accs[c], (unsigned long long)acc[c]);
+        if (c < nch && acc[c]) atomicAdd(&L.accs[c], (unsigned long long)acc[c]);
     __syncthreads();
-    if (tid < nch) atomicAdd(up->accepted[tid], accs[tid]);
+    if (tid < nch) atomicAdd(up->accepted[tid], L.accs[tid]);
 }
 
 __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict__ units,
                                                         int64_t t0, int32_t nsw, int64_t t_max)
 {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
     const VbUnit* up = units + blockIdx.x;
     switch (up->rpad) {
         case 1: vb_run<1>(up, smem, t0, nsw, t_max); break;
@@ -216,10 +306,18 @@ __global__ void __launch_bounds__(1024) vb_init_kernel(const VbUnit* __restrict_
 
 }  // namespace
 
-size_t vb_lds_bytes(int32_t n, int32_t rpad)
+int32_t vb_tile_entries(int threads) { return kEntPerLane * threads; }
+
+size_t vb_area_bytes(int threads)
+{
+    return 2 * (size_t)(threads + 8 + kEntPerLane * threads) * 4;
+}
+
+size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads)
 {
     const size_t sw = ((size_t)n * (size_t)rpad + 31) / 32;
-    return ((sw + 3) & ~(size_t)3) * 4 + 2 * kVbMaxChains * kVbXMax * 4 + kVbMaxChains * 8;
+    return ((sw + 3) & ~(size_t)3) * 4 + 2 * kVbMaxChains * kVbXMax * 4 + kVbMaxChains * 8 +
+           (size_t)threads * 16 + vb_area_bytes(threads);
 }
 
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStream_t s)

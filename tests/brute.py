@@ -46,9 +46,11 @@ def greedy_colour(n: int, A: np.ndarray):
     return colour
 
 
-def sweep_order(colour):
+def sweep_order(colour, A):
+    """Colour classes in order; inside a class by decreasing degree, then id."""
     n = len(colour)
-    return [v for c in range(max(colour) + 1) for v in range(n) if colour[v] == c]
+    deg = [int(np.count_nonzero(A[v])) for v in range(n)]
+    return sorted(range(n), key=lambda v: (colour[v], -deg[v], v))
 
 
 def accept_prob(x: np.ndarray, T: float, de_scale: float) -> np.ndarray:

@@ -61,7 +61,7 @@ def test_vb_tables_equal_oracle(n, c, seed, gid):
     assert np.array_equal(tab["J"], J)
     colour, ncol = oracle.greedy_colour(n, eu, ev)
     assert np.array_equal(tab["colour"], colour) and tab["n_colours"] == ncol
-    assert np.array_equal(tab["order"], oracle.sweep_order(colour, ncol))
+    assert np.array_equal(tab["order"], oracle.sweep_order(colour, ncol, oracle.degrees(n, eu, ev)))
     nb = _decode(tab, n)
     ref = {v: [] for v in range(n)}
     for u, v, j in zip(eu.tolist(), ev.tolist(), J.tolist()):

@@ -45,7 +45,7 @@ def test_vb_transient_energy_matches_master_equation(T):
     A = brute.coupling_matrix(n, eu, ev, J)
     S = brute.states(n)
     B = brute.bond_sum(S, A).astype(float)
-    order = brute.sweep_order(brute.greedy_colour(n, A))
+    order = brute.sweep_order(brute.greedy_colour(n, A), A)
     n_inst, t_max = 6000, 8
     bonds, times = _vb_many(n, eu, ev, J, T, n_inst, t_max, t_max)
     dist = np.full(1 << n, 1.0 / (1 << n))
@@ -69,7 +69,7 @@ def test_vb_equilibrium_is_boltzmann():
     eu, ev, J = _ring_with_chords(n, seed=3)
     A = brute.coupling_matrix(n, eu, ev, J)
     S = brute.states(n)
-    order = brute.sweep_order(brute.greedy_colour(n, A))
+    order = brute.sweep_order(brute.greedy_colour(n, A), A)
     pi = brute.boltzmann(S, A, T)
     assert np.allclose(brute.sweep(pi, S, A, order, T), pi, atol=1e-12)
     counts = np.zeros(1 << n)
@@ -157,7 +157,7 @@ def test_vb_observables_recomputed_from_configurations():
     assert o["overlap"][0, -1] == int(np.sum(s[0] * s[1]))
     # C(0, t_max) from the random start rebuilt from the INIT stream
     colour, ncol = oracle.greedy_colour(n, eu, ev)
-    order = oracle.sweep_order(colour, ncol)
+    order = oracle.sweep_order(colour, ncol, oracle.degrees(n, eu, ev))
     for r in range(2):
         init = np.zeros(n, np.int64)
         init[order] = [oracle.init_spin(1, 0, r, p) for p in range(n)]

@@ -74,17 +74,19 @@ def test_greedy_colouring_proper_and_greedy():
     assert list(colour) == ref
 
 
-def test_sweep_order_groups_classes_in_increasing_id():
+def test_sweep_order_groups_classes_by_decreasing_degree():
     n = 3000
     eu, ev, J, _ = oracle.er_graph(n, oracle.n_edges(n, 4.0), seed=5, graph_id=2)
     colour, ncol = oracle.greedy_colour(n, eu, ev)
-    order = oracle.sweep_order(colour, ncol)
+    deg = np.bincount(np.concatenate([eu, ev]), minlength=n)
+    order = oracle.sweep_order(colour, ncol, deg)
     assert sorted(order.tolist()) == list(range(n))
+    assert order.tolist() == sorted(range(n), key=lambda v: (colour[v], -deg[v], v))
     cs = colour[order]
     assert np.all(np.diff(cs) >= 0)
     for k in range(ncol):
-        ids = order[cs == k]
-        assert np.all(np.diff(ids) > 0)
+        d = deg[order[cs == k]]
+        assert np.all(np.diff(d) <= 0)
 
 
 def test_sk_couplings_symmetric_balanced_zero_diagonal():
