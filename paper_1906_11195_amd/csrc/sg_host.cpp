@@ -634,6 +634,11 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         U.ntiles = (int32_t)tiles[(size_t)plan[u].group].size();
         U.resident = resident[(size_t)plan[u].group];
         U.m2 = (int32_t)g.ent.size();
+        // chains of a unit share one graph, hence one seed (graphs are keyed by
+        // seed; an explicit edge list belongs to one instance)
+        U.key = d[plan[u].chains[0] / c->R].seed;
+        for (int32_t ch : plan[u].chains)
+            if (d[ch / c->R].seed != U.key) fail(SG_EINVAL);
         U.state = c->at<uint32_t>(off_state[u]);
         U.n = (int32_t)g.n;
         U.ncls = g.ncls;

@@ -33,6 +33,7 @@ struct VbUnit {
     int32_t resident;          // 1: whole adjacency kept in LDS for the launch
     int32_t m2;                // 2m entries
     int32_t pad0_;
+    uint64_t key;              // Philox key (seed) shared by every chain of the unit
     uint32_t* state;           // [state_words] packed spins between launches
     uint32_t* snap[kVbMaxChains];       // per chain: [K][words_n] position-order bits
     unsigned long long* accepted[kVbMaxChains];

@@ -8,13 +8,13 @@
 // LDS read of a neighbour returns its spin in every chain.
 //
 // A sweep visits colour class 0, 1, ...; inside a class all positions are
-// independent (no two are adjacent).  The classes are cut into tiles of at
-// most `threads` positions; lane i of the workgroup updates position
-// (p0 & ~7) + i of the tile, for every chain of the unit.  The tile's
-// adjacency (row starts and packed entries) sits in LDS: either the whole
-// graph is resident for the launch, or tiles are streamed from HBM with
-// coalesced loads issued one tile ahead (double buffer), so the load of tile
-// k+1 overlaps the updates of tile k.  One workgroup barrier ends each tile.
+// independent (no two are adjacent).  A class is cut into aligned chunks of 64
+// positions; wavefront w of the workgroup updates chunks w, w + W, ... of the
+// class (lane i takes position 64 b + i of block b), for every chain of the
+// unit.  Workgroup barriers separate classes only.  Each wavefront streams
+// the adjacency of its chunks straight from HBM through a two-stage register
+// pipeline: the row starts of the chunk after next and the entries of the
+// next chunk are in flight while the current chunk is updated.
 //
 // Metropolis rule (Methods; SI bipartite-graph section): with x = s_p h_p the
 // move is accepted if x <= 0, else iff r < thr[x], thr[x] = floor(2^32
@@ -29,7 +29,7 @@
 namespace sg {
 namespace {
 
-constexpr int kEntPerLane = 6;   // streamed-tile entries per lane
+constexpr int kDMax = 8;   // adjacency entries prefetched per position
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -44,10 +44,9 @@ struct VbLds {
     uint32_t* tlo;                // [8][64]
     unsigned long long* accs;     // [8]
     uint4* xch;                   // [threads] Philox blocks
-    int32_t* area;                // adjacency: resident graph or two tile buffers
 };
 
-__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr)
+__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw)
 {
     VbLds L;
     L.sp = smem;
@@ -55,68 +54,81 @@ __device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr)
     L.tlo = L.thi + kVbMaxChains * kVbXMax;
     L.accs = (unsigned long long*)(L.tlo + kVbMaxChains * kVbXMax);
     L.xch = (uint4*)(L.accs + kVbMaxChains);
-    L.area = (int32_t*)(L.xch + nthr);
     return L;
 }
 
-struct Prefetch {
-    int32_t r[2];
-    uint32_t e[kEntPerLane];
+// Chunk cursor of one wavefront: sweep s, colour class k, chunk j of the class
+// (the aligned block (cls[k] >> 6) + j of 64 positions).
+struct Cursor {
+    int32_t s, k, j;
 };
 
-__device__ __forceinline__ void tile_fetch(const VbUnit* __restrict__ up, const VbTile& T, int tid,
-                                           int nthr, Prefetch& pf)
+__device__ __forceinline__ int32_t n_chunks(const int32_t* __restrict__ cls, int32_t k)
 {
-    const int32_t nr = T.p1 - T.p0 + 1;
-    pf.r[0] = tid < nr ? up->row[T.p0 + tid] : 0;
-    pf.r[1] = tid + nthr < nr ? up->row[T.p0 + tid + nthr] : 0;
-#pragma unroll
-    for (int k = 0; k < kEntPerLane; ++k) {
-        const int32_t idx = tid + k * nthr;
-        pf.e[k] = idx < T.ne ? up->ent[T.e0 + idx] : 0u;
+    const int32_t lo = cls[k], hi = cls[k + 1];
+    return hi > lo ? ((hi - 1) >> 6) - (lo >> 6) + 1 : 0;
+}
+
+// Moves to the next chunk owned by wavefront `wave`; false past the launch.
+__device__ __forceinline__ bool cursor_next(Cursor& c, int W, int wave, int32_t ncls,
+                                            const int32_t* __restrict__ cls, int32_t nsw)
+{
+    c.j += W;
+    for (;;) {
+        if (c.j < n_chunks(cls, c.k)) return true;
+        c.j = wave;
+        if (++c.k == ncls) {
+            c.k = 0;
+            if (++c.s >= nsw) return false;
+        }
     }
 }
 
-__device__ __forceinline__ void tile_store(int32_t* buf, const VbTile& T, int tid, int nthr,
-                                           const Prefetch& pf)
+struct Stage {
+    int32_t q, r0, r1;
+    uint32_t e[kDMax];
+};
+
+__device__ __forceinline__ void load_rows(const VbUnit* __restrict__ up, const int32_t* __restrict__ cls,
+                                          const Cursor& c, int lane, Stage& st)
 {
-    const int32_t nr = T.p1 - T.p0 + 1;
-    if (tid < nr) buf[tid] = pf.r[0];
-    if (tid + nthr < nr) buf[tid + nthr] = pf.r[1];
-    uint32_t* eb = (uint32_t*)(buf + nthr + 8);
-#pragma unroll
-    for (int k = 0; k < kEntPerLane; ++k) {
-        const int32_t idx = tid + k * nthr;
-        if (idx < T.ne) eb[idx] = pf.e[k];
-    }
+    const int32_t lo = cls[c.k], hi = cls[c.k + 1];
+    st.q = (((lo >> 6) + c.j) << 6) + lane;
+    const bool act = st.q >= lo && st.q < hi;
+    st.r0 = act ? up->row[st.q] : 0;
+    st.r1 = act ? up->row[st.q + 1] : 0;
 }
 
-// Updates the positions of one tile for every chain of the unit.
+__device__ __forceinline__ void load_ents(const VbUnit* __restrict__ up, Stage& st)
+{
+    const int32_t deg = st.r1 - st.r0;
+#pragma unroll
+    for (int d = 0; d < kDMax; ++d) st.e[d] = d < deg ? up->ent[st.r0 + d] : 0u;
+}
+
+// Updates the positions of one chunk for every chain of the unit.
 template <int RPAD>
-__device__ __forceinline__ void vb_tile(const VbUnit* __restrict__ up, const VbLds& L,
-                                        const VbTile& T, const int32_t* __restrict__ rows,
-                                        const uint32_t* __restrict__ ents, int32_t rbase,
-                                        int32_t ebase, uint32_t t, int32_t nch, uint64_t my_seed,
-                                        uint32_t my_rep, uint32_t my_inst, uint32_t* acc)
+__device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const VbLds& L,
+                                         const Stage& st, int32_t lo, int32_t hi, uint32_t t,
+                                         int32_t nch, uint64_t key, uint32_t my_rep,
+                                         uint32_t my_inst, uint32_t* acc)
 {
     const int tid = threadIdx.x;
-    const int32_t q = (T.p0 & ~7) + tid;
+    const int32_t q = st.q;
     const int cc = tid & 7;
 
     // Philox block of chain cc for the group of q (shared by the 8 lanes).
     U4 A = U4{0, 0, 0, 0};
-    if (cc < nch) A = philox_stream(my_seed, (uint32_t)q >> 3, t, kDomSweepHi, my_rep, my_inst);
+    if (cc < nch) A = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepHi, my_rep, my_inst);
     L.xch[tid] = make_uint4(A.x, A.y, A.z, A.w);
     wave_sync();
-    if (q < T.p0 || q >= T.p1) return;
+    if (q < lo || q >= hi) return;
 
-    const int32_t r0 = rows[q - rbase];
-    const int32_t r1 = rows[q - rbase + 1];
     const uint32_t ob = (uint32_t)q * RPAD;
     const uint32_t own = L.sp[ob >> 5] >> (ob & 31u);
+    const int32_t deg = st.r1 - st.r0;
     uint32_t c0 = 0, c1 = 0;
-    for (int32_t e = r0; e < r1; ++e) {
-        const uint32_t en = ents[e - ebase];
+    auto bond = [&](uint32_t en) {
         const uint32_t qb = (en & 0x7fffffffu) * RPAD;
         // bit c of f is 1 iff the bond (q, neighbour) is unsatisfied in chain c
         const uint32_t f = (L.sp[qb >> 5] >> (qb & 31u)) ^ own ^ (uint32_t)((int32_t)en >> 31);
@@ -127,8 +139,14 @@ __device__ __forceinline__ void vb_tile(const VbUnit* __restrict__ up, const VbL
             c0 += ((f & 0xFu) * 0x00204081u) & 0x01010101u;
             if (RPAD == 8) c1 += (((f >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
         }
+    };
+#pragma unroll
+    for (int d = 0; d < kDMax; ++d) {
+        if (!__any(d < deg)) break;
+        if (d < deg) bond(st.e[d]);
     }
-    const int32_t deg = r1 - r0;
+    for (int32_t d = kDMax; d < deg; ++d) bond(up->ent[st.r0 + d]);
+
     const uint32_t* gx = (const uint32_t*)(L.xch + (tid & ~7));
     const uint32_t hsel = (uint32_t)tid & 7u;
     uint32_t fl = 0;
@@ -143,8 +161,7 @@ __device__ __forceinline__ void vb_tile(const VbUnit* __restrict__ up, const VbL
             const uint32_t rh = (gx[4 * c + (hsel >> 1)] >> (16u * (hsel & 1u))) & 0xffffu;
             flip = rh < th;
             if (rh == th) {
-                const U4 B = philox_stream(up->seed[c], (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c],
-                                           up->inst[c]);
+                const U4 B = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
                 flip = half_word(B, hsel) < L.tlo[c * kVbXMax + x];
             }
         }
@@ -178,9 +195,10 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
                        int64_t t_max)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int32_t sw = up->state_words, n = up->n, nch = up->nch;
-    const VbLds L = vb_carve(smem, sw, nthr);
-    const bool res = up->resident != 0;
+    const int lane = tid & 63, wave = tid >> 6, W = nthr >> 6;
+    const int32_t sw = up->state_words, nch = up->nch, ncls = up->ncls;
+    const int32_t* __restrict__ cls = up->cls;
+    const VbLds L = vb_carve(smem, sw);
 
     for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = up->state[w];
     for (int i = tid; i < kVbMaxChains * kVbXMax; i += nthr) {
@@ -188,27 +206,22 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
         L.tlo[i] = (&up->thr_lo[0][0])[i];
     }
     if (tid < kVbMaxChains) L.accs[tid] = 0;
-    if (res) {
-        for (int32_t i = tid; i <= n; i += nthr) L.area[i] = up->row[i];
-        uint32_t* re = (uint32_t*)(L.area + n + 1);
-        for (int32_t i = tid; i < up->m2; i += nthr) re[i] = up->ent[i];
-    }
     // chain whose Philox block this lane computes
+    const uint64_t key = up->key;
     const int cc = tid & 7;
-    const uint64_t my_seed = cc < nch ? up->seed[cc] : 0ull;
     const uint32_t my_rep = cc < nch ? up->rep[cc] : 0u;
     const uint32_t my_inst = cc < nch ? up->inst[cc] : 0u;
 
-    const int32_t nt = up->ntiles;
-    const VbTile* __restrict__ tiles = up->tiles;
-    const int64_t total = (int64_t)nsw * nt;
-    const int32_t bufw = nthr + 8 + kEntPerLane * nthr;
-    Prefetch pf;
-    if (!res && total > 0) {
-        const VbTile T0 = tiles[0];
-        tile_fetch(up, T0, tid, nthr, pf);
-        tile_store(L.area, T0, tid, nthr, pf);
-        if (total > 1) tile_fetch(up, tiles[1 % nt], tid, nthr, pf);
+    // pipeline: E = chunk to update next (rows + entries), R = the one after
+    // (rows only)
+    Stage E, R;
+    Cursor cR{0, 0, wave - W};
+    bool haveR = nsw > 0 && cursor_next(cR, W, wave, ncls, cls, nsw);
+    if (haveR) {
+        load_rows(up, cls, cR, lane, E);
+        load_ents(up, E);
+        haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
+        if (haveR) load_rows(up, cls, cR, lane, R);
     }
     __syncthreads();
 
@@ -216,32 +229,29 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) acc[c] = 0;
 
-    int32_t ti = 0, s = 0;
-    for (int64_t it = 0; it < total; ++it) {
+    for (int32_t s = 0; s < nsw; ++s) {
         const uint32_t t = (uint32_t)(t0 + s);
-        const VbTile T = tiles[ti];
-        if (res) {
-            vb_tile<RPAD>(up, L, T, L.area, (const uint32_t*)(L.area + n + 1), 0, 0, t, nch, my_seed,
-                          my_rep, my_inst, acc);
-        } else {
-            const int32_t* buf = L.area + (int32_t)(it & 1) * bufw;
-            vb_tile<RPAD>(up, L, T, buf, (const uint32_t*)(buf + nthr + 8), T.p0, T.e0, t, nch,
-                          my_seed, my_rep, my_inst, acc);
-            if (it + 1 < total) {
-                const VbTile Tn = tiles[ti + 1 == nt ? 0 : ti + 1];
-                tile_store(L.area + (int32_t)((it + 1) & 1) * bufw, Tn, tid, nthr, pf);
+        for (int32_t k = 0; k < ncls; ++k) {
+            const int32_t lo = cls[k], hi = cls[k + 1];
+            const int32_t nck = n_chunks(cls, k);
+            for (int32_t j = wave; j < nck; j += W) {
+                const Stage cur = E;
+                if (haveR) {
+                    E.q = R.q;
+                    E.r0 = R.r0;
+                    E.r1 = R.r1;
+                    load_ents(up, E);
+                    haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
+                    if (haveR) load_rows(up, cls, cR, lane, R);
+                }
+                vb_chunk<RPAD>(up, L, cur, lo, hi, t, nch, key, my_rep, my_inst, acc);
             }
+            __syncthreads();
         }
-        __syncthreads();
-        if (!res && it + 2 < total) tile_fetch(up, tiles[(ti + 2) % nt], tid, nthr, pf);
-        if (++ti == nt) {
-            ti = 0;
-            ++s;
-            const int64_t tn = t0 + s;
-            if (tn <= t_max && (tn & (tn - 1)) == 0) {
-                vb_snapshot<RPAD>(up, L.sp, 1 + (63 - __clzll((unsigned long long)tn)));
-                __syncthreads();
-            }
+        const int64_t tn = t0 + s + 1;
+        if (tn <= t_max && (tn & (tn - 1)) == 0) {
+            vb_snapshot<RPAD>(up, L.sp, 1 + (63 - __clzll((unsigned long long)tn)));
+            __syncthreads();
         }
     }
 
@@ -306,18 +316,15 @@ __global__ void __launch_bounds__(1024) vb_init_kernel(const VbUnit* __restrict_
 
 }  // namespace
 
-int32_t vb_tile_entries(int threads) { return kEntPerLane * threads; }
+int32_t vb_tile_entries(int threads) { return 6 * threads; }
 
-size_t vb_area_bytes(int threads)
-{
-    return 2 * (size_t)(threads + 8 + kEntPerLane * threads) * 4;
-}
+size_t vb_area_bytes(int threads) { return 0 * (size_t)threads; }
 
 size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads)
 {
     const size_t sw = ((size_t)n * (size_t)rpad + 31) / 32;
     return ((sw + 3) & ~(size_t)3) * 4 + 2 * kVbMaxChains * kVbXMax * 4 + kVbMaxChains * 8 +
-           (size_t)threads * 16 + vb_area_bytes(threads);
+           (size_t)threads * 16;
 }
 
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStream_t s)
