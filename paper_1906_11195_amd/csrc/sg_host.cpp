@@ -161,37 +161,6 @@ void vb_tables(VbGraph& g)
     g.row[(size_t)n] = (int32_t)e;
 }
 
-// Cuts every colour class into tiles of at most `threads` lanes (lane i takes
-// position (p0 & ~7) + i).  A streamed tile also holds at most
-// vb_tile_entries(threads) adjacency entries.  Tiles end on a multiple of 8
-// unless they end their class, so that an aligned group of 8 positions never
-// straddles two tiles of one class.
-std::vector<VbTile> vb_tile_plan(const VbGraph& g, int threads, bool resident)
-{
-    std::vector<VbTile> out;
-    const int32_t ecap = vb_tile_entries(threads);
-    for (int32_t k = 0; k < g.ncls; ++k) {
-        const int32_t end = g.cls[(size_t)k + 1];
-        int32_t p = g.cls[(size_t)k];
-        while (p < end) {
-            int32_t q = std::min<int32_t>(end, (p & ~7) + threads);
-            if (!resident && g.row[(size_t)q] - g.row[(size_t)p] > ecap) {
-                int32_t lo = p + 1, hi = q;   // largest q' with at most ecap entries
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) / 2;
-                    if (g.row[(size_t)mid] - g.row[(size_t)p] <= ecap) lo = mid;
-                    else hi = mid - 1;
-                }
-                q = lo & ~7;
-                if (q <= p) q = std::min<int32_t>(end, (p & ~7) + 8);
-            }
-            out.push_back(VbTile{p, q, g.row[(size_t)p], g.row[(size_t)q] - g.row[(size_t)p]});
-            p = q;
-        }
-    }
-    return out;
-}
-
 bool finite_nonneg_T(double T) { return !(T < 0.0) && !std::isnan(T); }
 
 void check_vb_desc(const sg_vb_desc& d)
@@ -552,22 +521,22 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     }
     for (const auto& u : plan)
         if (vb_lds_bytes((int32_t)graphs[(size_t)u.group].n, u.rpad, threads) > lds_cap) fail(SG_ENOTSUP);
-    std::vector<std::vector<VbTile>> tiles(n_groups);
-    std::vector<int32_t> resident(n_groups);
-    for (size_t gi = 0; gi < n_groups; ++gi) {
-        const VbGraph& g = graphs[gi];
-        resident[gi] = (size_t)(g.n + 1 + (int64_t)g.ent.size()) * 4 <= vb_area_bytes(threads);
-        tiles[gi] = vb_tile_plan(g, threads, resident[gi] != 0);
+    // small graphs keep their whole adjacency in LDS for the launch
+    std::vector<int32_t> resident(n_groups, 1);
+    for (const auto& u : plan) {
+        const VbGraph& g = graphs[(size_t)u.group];
+        if (vb_lds_bytes((int32_t)g.n, u.rpad, threads) + vb_resident_bytes((int32_t)g.n, (int32_t)g.ent.size()) >
+            lds_cap)
+            resident[(size_t)u.group] = 0;
     }
 
     // device layout
     Arena A;
-    std::vector<size_t> off_row(n_groups), off_ent(n_groups), off_cls(n_groups), off_tiles(n_groups);
+    std::vector<size_t> off_row(n_groups), off_ent(n_groups), off_cls(n_groups);
     for (size_t gi = 0; gi < n_groups; ++gi) {
         off_row[gi] = A.take(graphs[gi].row.size() * 4);
         off_ent[gi] = A.take(std::max<size_t>(1, graphs[gi].ent.size()) * 4);
         off_cls[gi] = A.take(graphs[gi].cls.size() * 4);
-        off_tiles[gi] = A.take(std::max<size_t>(1, tiles[gi].size()) * sizeof(VbTile));
     }
     std::vector<size_t> off_state(plan.size());
     for (size_t u = 0; u < plan.size(); ++u) {
@@ -605,9 +574,6 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         if (!g.ent.empty())
             hip_check(hipMemcpy(c->at<void>(off_ent[gi]), g.ent.data(), g.ent.size() * 4, hipMemcpyHostToDevice));
         hip_check(hipMemcpy(c->at<void>(off_cls[gi]), g.cls.data(), g.cls.size() * 4, hipMemcpyHostToDevice));
-        if (!tiles[gi].empty())
-            hip_check(hipMemcpy(c->at<void>(off_tiles[gi]), tiles[gi].data(), tiles[gi].size() * sizeof(VbTile),
-                                hipMemcpyHostToDevice));
     }
     for (int32_t i = 0; i < count; ++i) {
         if (d[i].start != SG_START_GIVEN) continue;
@@ -630,8 +596,6 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         U.row = c->at<int32_t>(off_row[(size_t)plan[u].group]);
         U.ent = c->at<uint32_t>(off_ent[(size_t)plan[u].group]);
         U.cls = c->at<int32_t>(off_cls[(size_t)plan[u].group]);
-        U.tiles = c->at<VbTile>(off_tiles[(size_t)plan[u].group]);
-        U.ntiles = (int32_t)tiles[(size_t)plan[u].group].size();
         U.resident = resident[(size_t)plan[u].group];
         U.m2 = (int32_t)g.ent.size();
         // chains of a unit share one graph, hence one seed (graphs are keyed by
@@ -665,7 +629,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
             c->chain_loc[(size_t)ch] = {(int32_t)u, k};
         }
         c->units[u] = U;
-        c->vb_lds = std::max(c->vb_lds, vb_lds_bytes(U.n, U.rpad, threads));
+        c->vb_lds = std::max(c->vb_lds, vb_lds_bytes(U.n, U.rpad, threads) +
+                                            (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
         c->bond_lds = std::max(c->bond_lds, (size_t)(((U.nch * U.words_n + 1) & ~1) * 4 + kVbMaxChains * 8));
         c->updates_per_sweep += g.n * U.nch;
     }
@@ -758,10 +723,11 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     }
 
     Arena A;
-    std::vector<size_t> off_J(jrep.size());
+    std::vector<size_t> off_J(jrep.size()), off_Jb(jrep.size());
     for (size_t j = 0; j < jrep.size(); ++j) {
         const int64_t n = d[jrep[j]].n;
         off_J[j] = A.take((size_t)(n * n));
+        off_Jb[j] = A.take((size_t)n * (size_t)((n + 31) / 32) * 4);
     }
     std::vector<size_t> off_thr((size_t)count);
     for (int32_t i = 0; i < count; ++i) off_thr[(size_t)i] = A.take(thr[(size_t)i].size() * 8);
@@ -792,17 +758,25 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     c->arena_bytes = A.size;
     c->arena = c->dev_alloc(A.size);
 
-    // couplings: generated on the host in parallel, or copied
+    // couplings: generated on the host in parallel, or copied; int8 rows for
+    // the MFMA contractions and bit-packed rows (bit 1 = -1, 8x fewer bytes)
+    // for the field updates of the sweep
     parallel_for(jrep.size(), [&](size_t j) {
         const sg_sk_desc& r = d[jrep[j]];
-        const int64_t n = r.n;
-        if (r.J) {
-            hip_check(hipMemcpy(c->at<void>(off_J[j]), r.J, (size_t)(n * n), hipMemcpyHostToDevice));
-        } else {
-            std::vector<int8_t> J((size_t)(n * n));
+        const int64_t n = r.n, wn = (n + 31) / 32;
+        std::vector<int8_t> J;
+        const int8_t* src = r.J;
+        if (!src) {
+            J.resize((size_t)(n * n));
             sk_generate(n, r.seed, r.graph_id, J.data());
-            hip_check(hipMemcpy(c->at<void>(off_J[j]), J.data(), J.size(), hipMemcpyHostToDevice));
+            src = J.data();
         }
+        hip_check(hipMemcpy(c->at<void>(off_J[j]), src, (size_t)(n * n), hipMemcpyHostToDevice));
+        std::vector<uint32_t> Jb((size_t)(n * wn), 0u);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = 0; k < n; ++k)
+                if (src[i * n + k] < 0) Jb[(size_t)(i * wn + (k >> 5))] |= 1u << (k & 31);
+        hip_check(hipMemcpy(c->at<void>(off_Jb[j]), Jb.data(), Jb.size() * 4, hipMemcpyHostToDevice));
     });
     for (int32_t i = 0; i < count; ++i)
         hip_check(hipMemcpy(c->at<void>(off_thr[(size_t)i]), thr[(size_t)i].data(), thr[(size_t)i].size() * 8,
@@ -818,11 +792,15 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
             SkChain S;
             std::memset(&S, 0, sizeof(S));
             S.J = c->at<int8_t>(off_J[(size_t)jslot[(size_t)i]]);
+            S.Jb = c->at<uint32_t>(off_Jb[(size_t)jslot[(size_t)i]]);
             S.state = c->at<uint32_t>(off_state[ch]);
             S.H = c->at<int32_t>(off_H[ch]);
             S.snap = c->at<uint32_t>(off_snap[ch]);
-            S.bond = c->at<long long>(off_bond) + ch * (size_t)c->K;
             S.accepted = c->at<unsigned long long>(off_acc) + ch;
+            // slope of log(thr[x] / 2^32) in x, a starting guess for the
+            // kernel's exact search of the largest accepted x
+            const double slope = 2.0 / d[i].T / std::sqrt((double)d[i].n);
+            S.xslope = std::isinf(d[i].T) ? 0.0f : (d[i].T == 0.0 ? INFINITY : (float)slope);
             S.thr = c->at<uint64_t>(off_thr[(size_t)i]);
             S.seed = d[i].seed;
             S.inst = d[i].instance_id;
@@ -867,11 +845,10 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
     hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
     hip_check(zero_i64((long long*)c->err_d, 1, nullptr));
-    c->sk_threads = o && o->threads_per_unit ? o->threads_per_unit : 256;
+    c->sk_threads = sk_threads();
     c->sk_lds = sk_lds_bytes(c->sk_max_n);
     hip_check(sk_init(c->sk_d, c->n_chains, 256, nullptr));
     hip_check(sk_recompute(c->sks_d, count, c->sk_d, c->sk_max_n, 0, c->err_d, nullptr));
-    hip_check(sk_bond_t0(c->sk_d, c->n_chains, nullptr));
     hip_check(hipDeviceSynchronize());
 }
 
@@ -977,7 +954,7 @@ sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream)
                 const int64_t to_check = c->period - (c->t_done % c->period);
                 const int64_t chunk = std::min(left, to_check);
                 hip_check(sk_sweep(c->sk_d, c->n_chains, c->sk_threads, c->sk_lds, c->t_done, (int32_t)chunk,
-                                   c->t_max, s));
+                                   c->t_max, c->err_d, s));
                 c->t_done += chunk;
                 left -= chunk;
                 if (c->t_done % c->period == 0)
@@ -1002,9 +979,14 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
         out->k_done = kd;
         out->t_done = c->t_done;
         if (flags & SG_MEASURE_OBS) {
-            if (c->kind == 0)
+            if (c->kind == 0) {
                 hip_check(vb_bond(c->units_d, (int)c->units.size(), kd, c->bond_d, c->unit_chain_ids_d, K,
                                   std::min(1024, c->vb_threads), c->bond_lds, s));
+            } else {
+                // accumulates 2 B per (chain, grid time); halved below
+                hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * K, s));
+                hip_check(sk_bond(c->sks_d, c->count, c->sk_d, c->sk_max_n, R, kd, K, c->bond_d, s));
+            }
             hip_check(measure_overlap(c->mc_d, c->pairs_d, c->n_pairs, kd, K, c->overlap_d, s));
             hip_check(zero_i64(c->gram_d, (size_t)c->n_chains * K * K, s));
             hip_check(measure_gram(c->mc_d, c->n_chains, kd, K, c->max_words, c->gram_d, s));
@@ -1023,7 +1005,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
                 for (int32_t k = 0; k < K; ++k) out->times[k] = c->times[(size_t)k];
             if (out->bond)
                 for (size_t i = 0; i < bond.size(); ++i)
-                    out->bond[i] = (int64_t)i % K < kd ? (int64_t)bond[i] : 0;
+                    out->bond[i] = (int64_t)i % K < kd ? (int64_t)bond[i] / (c->kind == 1 ? 2 : 1) : 0;
             if (out->overlap && c->n_pairs)
                 for (size_t i = 0; i < (size_t)c->n_pairs * K; ++i)
                     out->overlap[i] = (int64_t)i % K < kd ? (int64_t)ovl[i] : 0;
@@ -1072,7 +1054,8 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
         }
     });
     if (st != SG_OK) return st;
-    return err_flag ? SG_EPARITY : SG_OK;
+    if (err_flag & 2) return SG_EDEVICE;   // a sweep pipeline stalled and aborted
+    return (err_flag & 1) ? SG_EPARITY : SG_OK;
 }
 
 void sg_free(sg_ctx* c)

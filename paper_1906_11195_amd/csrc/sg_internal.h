@@ -16,23 +16,12 @@ constexpr int kSkThrLds = 1024;    // SK threshold entries cached in LDS
 // One VB work unit = one workgroup: a graph in sweep (colour) order and up to
 // eight chains that share it.  The chains' spins live in LDS during a launch,
 // vertex-major: position p holds `rpad` bits, bit c belongs to chain c.
-// A tile is a run of positions [p0, p1) of one colour class whose adjacency
-// (row starts p0..p1 and entries e0 .. e0+ne) is staged in LDS at once.
-// Lane i of the workgroup takes position (p0 & ~7) + i; p1 <= (p0 & ~7) +
-// threads; a tile ends on a multiple of 8 unless it ends its class.
-struct VbTile {
-    int32_t p0, p1, e0, ne;
-};
-
 struct VbUnit {
     const int32_t* row;        // [n+1] adjacency row starts, sweep order
     const uint32_t* ent;       // [2m] neighbour position | (J < 0) << 31
     const int32_t* cls;        // [ncls+1] first position of each colour class
-    const VbTile* tiles;       // [ntiles] one sweep, class by class
-    int32_t ntiles;
     int32_t resident;          // 1: whole adjacency kept in LDS for the launch
     int32_t m2;                // 2m entries
-    int32_t pad0_;
     uint64_t key;              // Philox key (seed) shared by every chain of the unit
     uint32_t* state;           // [state_words] packed spins between launches
     uint32_t* snap[kVbMaxChains];       // per chain: [K][words_n] position-order bits
@@ -55,10 +44,10 @@ struct VbUnit {
 // One SK chain (a replica of an instance).
 struct SkChain {
     const int8_t* J;           // [n][n]
+    const uint32_t* Jb;        // [n][words_n] bit-packed rows, bit 1 = coupling -1
     uint32_t* state;           // [words_n] position-order bits (1 = spin -1)
     int32_t* H;                // [n] local fields between launches
     uint32_t* snap;            // [K][words_n]
-    long long* bond;           // [K]
     unsigned long long* accepted;
     const uint64_t* thr;       // [thr_len] thresholds (uint64), x < thr_len
     uint64_t seed;
@@ -70,7 +59,7 @@ struct SkChain {
     int32_t init_mode;
     const uint32_t* given;     // position-order bits when GIVEN
     int32_t sample;            // index of the instance in the context
-    int32_t pad_;
+    float xslope;              // 2 beta / sqrt(N): thr[x] ~ 2^32 exp(-xslope x)
 };
 
 // SK instance (sample) for the exact field recompute: all its chains.
@@ -92,19 +81,21 @@ struct MeasureChain {
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t lds_bytes, hipStream_t s);
 hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, int64_t t0,
                     int32_t n_sweeps, int64_t t_max, hipStream_t s);
-// Entries a streamed tile may hold, and the LDS a unit needs, for a launch
-// with `threads` lanes per workgroup.
-int32_t vb_tile_entries(int threads);
-size_t vb_area_bytes(int threads);
+// LDS a unit needs for a launch with `threads` lanes per workgroup, and the
+// extra LDS that keeps its whole adjacency resident.
 size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads);
+size_t vb_resident_bytes(int32_t n, int32_t m2);
 
+// err_flag bit 0: recompute mismatch; bit 1: the sweep pipeline stalled.
 hipError_t sk_init(const SkChain* chains, int n_chains, int threads, hipStream_t s);
 hipError_t sk_recompute(const SkSample* samples, int n_samples, const SkChain* chains,
                         int max_n, int check, int* err_flag, hipStream_t s);
-hipError_t sk_bond_t0(const SkChain* chains, int n_chains, hipStream_t s);
+hipError_t sk_bond(const SkSample* samples, int n_samples, const SkChain* chains, int max_n,
+                   int max_nch, int k_done, int k_cap, long long* out, hipStream_t s);
 hipError_t sk_sweep(const SkChain* chains, int n_chains, int threads, size_t lds_bytes, int64_t t0,
-                    int32_t n_sweeps, int64_t t_max, hipStream_t s);
+                    int32_t n_sweeps, int64_t t_max, int* err_flag, hipStream_t s);
 size_t sk_lds_bytes(int32_t n);
+int sk_threads();
 
 hipError_t vb_bond(const VbUnit* units, int n_units, int k_done, long long* bond_out,
                    const int32_t* unit_chain_ids, int k_cap, int threads, size_t lds_bytes,

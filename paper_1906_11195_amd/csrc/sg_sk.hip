@@ -1,23 +1,36 @@
 // Sherrington-Kirkpatrick Metropolis sweeps on gfx950.
 //
 // The SK sweep visits i = 0..N-1 in a fixed order (SI, SK section), so a chain
-// is inherently sequential.  One workgroup runs one chain with its integer
-// local fields H_i = sum_j J_ij s_j resident in LDS.  The sweep is cut into
-// blocks of 64 consecutive spins, one per wavefront lane:
-//   * every lane decides its spin speculatively, as if no earlier spin of the
-//     block flipped (the Philox draw of a position does not depend on the
-//     attempt, so a decision made with the exact field is final);
-//   * a ballot finds the first accepting lane j; lanes before j are final
-//     rejections, lane j flips, the fields of lanes after j are patched with
-//     row j of the 64 x 64 coupling tile held in LDS, and the scan resumes
-//     at j + 1;
-//   * after the block every thread applies the rank-f update
-//     H_k += 2 s_j J_jk of the f flipped rows to all N fields.
-// The result equals the plain sequential sweep exactly (integer fields).
+// is sequential.  One workgroup runs one chain with its integer local fields
+// H_i = sum_j J_ij s_j resident in LDS, split into three roles that form a
+// pipeline over blocks of 64 consecutive spins (block g of the launch is block
+// b = g mod NB of sweep t0 + g / NB):
 //
-// Every `period` sweeps the fields are recomputed exactly as H = J S with
-// int8 MFMA (v_mfma_i32_16x16x64_i8, int32 accumulation) and compared with
-// the incremental ones; a mismatch raises the context's error flag.
+//  * prep wavefront (ahead of the decider by up to kRing blocks): draws the
+//    acceptance uniform r of every position of the block (two Philox streams)
+//    and turns it into xmax = max{x : r < thr[x]}, so that a spin with
+//    x = s_i H_i flips iff x <= xmax; it also fetches, from the bit-packed
+//    couplings, the 64 x 64 tile of the block's own rows and the tile of the
+//    previous block's rows restricted to this block's columns.
+//  * decider wavefront: lane i owns spin 64 b + i.  It corrects the block's
+//    fields for the flips of the previous block (previous-block tile), then
+//    decides the block speculatively: every lane compares x with xmax as if no
+//    earlier spin of the block flipped; a ballot finds the first flip j, lane j
+//    flips, every lane's field is patched with row j of the block tile, and the
+//    scan resumes at j + 1.  Decisions made with exact fields are final, so the
+//    result is the plain sequential sweep.  The block's flips are published to
+//    a ring buffer.
+//  * updater wavefronts: apply each published block's flips to all other fields
+//    (H_k += 2 s_j J_jk, rows read bit-packed, 16 fields per lane), lagging one
+//    block behind; they skip the flipped block (patched in the decider) and the
+//    next block (corrected by the decider from its tile), except for the last
+//    block of a launch.
+//
+// Every `period` sweeps the fields are recomputed exactly as H = J S with int8
+// MFMA (v_mfma_i32_16x16x64_i8, int32 accumulation) and compared with the
+// incremental ones; a mismatch raises the context's error flag.  Bond sums
+// B = (1/2) s^T J s of the snapshots are computed the same way at measurement
+// time.
 #include "sg_internal.h"
 #include "sg_philox.h"
 
@@ -26,155 +39,268 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+constexpr int kRing = 4;            // blocks in flight between the roles
+constexpr int kUpdWaves = 4;        // updater wavefronts
+constexpr int kSkThreads = 64 * (2 + kUpdWaves);
+constexpr int kSpinLimit = 1 << 22; // bounded waits: a stuck pipeline aborts
+
 struct SkLds {
-    int32_t* H;
-    uint32_t* bits;
-    unsigned long long* thr;
-    int8_t* tile;
-    int32_t* flips;
-    int32_t* misc;        // [0] = number of flips in the block
-    long long* red;       // reduction slot
+    int32_t* H;                 // [n]
+    uint32_t* bits;             // [wn + 2]
+    unsigned long long* thr;    // [kSkThrLds]
+    int32_t* xm;                // [kRing][64]
+    uint32_t* tile;             // [kRing][64][4]: diag word 0, 1, prev word 0, 1
+    int32_t* flips;             // [kRing][64]: local row | (new spin -1) << 31
+    int32_t* nflip;             // [kRing]
+    int32_t* sync;              // decided, applied, prepared, abort, done[kRing]
 };
 
 __device__ __forceinline__ SkLds sk_carve(uint8_t* base, int32_t n, int32_t wn)
 {
     SkLds L;
     size_t off = 0;
-    L.H = (int32_t*)(base + off);
-    off += ((size_t)n * 4 + 15) & ~(size_t)15;
-    L.bits = (uint32_t*)(base + off);
-    off += ((size_t)(wn + 2) * 4 + 15) & ~(size_t)15;
-    L.thr = (unsigned long long*)(base + off);
-    off += (size_t)kSkThrLds * 8;
-    L.tile = (int8_t*)(base + off);
-    off += (size_t)kSkTile * kSkTile;
-    L.flips = (int32_t*)(base + off);
-    off += kSkTile * 4;
-    L.red = (long long*)(base + off);
-    off += 16;
-    L.misc = (int32_t*)(base + off);
+    auto take = [&](size_t bytes) {
+        uint8_t* p = base + off;
+        off += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    L.H = (int32_t*)take((size_t)n * 4);
+    L.bits = (uint32_t*)take((size_t)(wn + 2) * 4);
+    L.thr = (unsigned long long*)take((size_t)kSkThrLds * 8);
+    L.xm = (int32_t*)take((size_t)kRing * 64 * 4);
+    L.tile = (uint32_t*)take((size_t)kRing * 64 * 16);
+    L.flips = (int32_t*)take((size_t)kRing * 64 * 4);
+    L.nflip = (int32_t*)take((size_t)kRing * 4);
+    L.sync = (int32_t*)take((size_t)(4 + kRing) * 4);
     return L;
 }
 
-__global__ void __launch_bounds__(256) sk_sweep_kernel(const SkChain* __restrict__ chains,
-                                                       int64_t t0, int32_t nsw, int64_t t_max)
+enum { kDecided = 0, kApplied = 1, kPrepared = 2, kAbort = 3, kDone = 4 };
+
+__device__ __forceinline__ int ld_acq(int32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void st_rel(int32_t* p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Waits (whole wavefront) until *p >= target.  After kSpinLimit polls the
+// pipeline is declared stuck: the abort flag releases every other wait and
+// the context's error flag reports it.
+__device__ __forceinline__ void wait_ge(const SkLds& L, int32_t idx, int32_t target, int* err)
+{
+    int spins = 0;
+    while (ld_acq(&L.sync[idx]) < target) {
+        if (ld_acq(&L.sync[kAbort])) return;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+            st_rel(&L.sync[kAbort], 1);
+            atomicOr(err, 2);
+            return;
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_release()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ unsigned long long thr_at(const SkLds& L, const SkChain* ch,
+                                                      int32_t cached, int32_t x)
+{
+    if (x >= ch->thr_len) return 0ull;
+    return x < cached ? L.thr[x] : ch->thr[x];
+}
+
+__global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __restrict__ chains,
+                                                              int64_t t0, int32_t nsw,
+                                                              int64_t t_max, int* err)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t sk_smem[];
     const SkChain* ch = chains + blockIdx.x;
     const int32_t n = ch->n, wn = ch->words_n;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    SkLds L = sk_carve(sk_smem, n, wn);
-    const int8_t* __restrict__ J = ch->J;
-    const int32_t thr_len = ch->thr_len;
-    const int32_t thr_cached = min(thr_len, kSkThrLds);
+    const int lane = tid & 63, wave = tid >> 6;
+    const SkLds L = sk_carve(sk_smem, n, wn);
+    const int32_t cached = min(ch->thr_len, kSkThrLds);
 
     for (int32_t i = tid; i < n; i += nthr) L.H[i] = ch->H[i];
     for (int32_t w = tid; w < wn + 2; w += nthr) L.bits[w] = w < wn ? ch->state[w] : 0u;
-    for (int32_t x = tid; x < thr_cached; x += nthr) L.thr[x] = ch->thr[x];
+    for (int32_t x = tid; x < cached; x += nthr) L.thr[x] = ch->thr[x];
+    if (tid < 4 + kRing) L.sync[tid] = 0;
     __syncthreads();
 
-    const int32_t nb = (n + kSkTile - 1) / kSkTile;
-    const int lane = tid & 63;
-    uint32_t acc = 0;
+    const int32_t NB = (n + 63) >> 6;
+    const int64_t total = (int64_t)nsw * NB;
+    const uint32_t* __restrict__ Jb = ch->Jb;
 
-    for (int32_t s = 0; s < nsw; ++s) {
-        const uint32_t t = (uint32_t)(t0 + s);
-        for (int32_t b = 0; b < nb; ++b) {
-            const int32_t base = b * kSkTile;
-            for (int32_t idx = tid; idx < kSkTile * kSkTile; idx += nthr) {
-                const int32_t r = idx >> 6, c = idx & 63;
-                const int32_t pr = base + r, pc = base + c;
-                L.tile[idx] = (pr < n && pc < n) ? J[(int64_t)pr * n + pc] : (int8_t)0;
+    if (wave == 1) {
+        // ---------------- prep ----------------
+        int32_t b = 0, s = 0;
+        for (int64_t g = 0; g < total; ++g) {
+            if (g >= kRing) wait_ge(L, kDecided, (int32_t)(g - kRing + 1), err);
+            const int slot = (int)(g & (kRing - 1));
+            const int32_t p = (b << 6) + lane;
+            const uint32_t t = (uint32_t)(t0 + s);
+            const U4 A = philox_stream(ch->seed, (uint32_t)p >> 3, t, kDomSweepHi, ch->rep, ch->inst);
+            const U4 B = philox_stream(ch->seed, (uint32_t)p >> 3, t, kDomSweepLo, ch->rep, ch->inst);
+            const uint32_t r = (half_word(A, (uint32_t)p & 7u) << 16) | half_word(B, (uint32_t)p & 7u);
+            // starting guess from the logarithm, then exact fix-up on the table
+            int32_t x0;
+            const float slope = ch->xslope;
+            if (slope <= 0.0f) {
+                x0 = ch->thr_len - 1;
+            } else {
+                const float lv = 22.18070977791825f - __logf((float)r + 1.0f);
+                const float xf = lv / slope;
+                x0 = xf >= (float)(ch->thr_len - 1) ? ch->thr_len - 1 : (xf <= 0.0f ? 0 : (int32_t)xf);
             }
-            __syncthreads();
-            if (tid < 64) {
-                const int32_t p = base + lane;
-                const bool act = p < n;
-                int32_t Hp = act ? L.H[p] : 0;
-                uint32_t sb = act ? (L.bits[p >> 5] >> (p & 31)) & 1u : 0u;
-                const U4 A = philox_stream(ch->seed, (uint32_t)(p >> 3), t, kDomSweepHi, ch->rep,
-                                           ch->inst);
-                const uint32_t rh = half_word(A, (uint32_t)(p & 7));
-                uint32_t rl = 0;
-                bool have_lo = false;
-                int32_t start = 0, nf = 0;
-                while (true) {
-                    const int32_t x = sb ? -Hp : Hp;
-                    const bool cand = act && lane >= start;
-                    bool accept = false, tie = false;
-                    uint32_t tlo = 0;
-                    if (cand) {
-                        if (x <= 0) {
-                            accept = true;
-                        } else {
-                            unsigned long long th = 0;
-                            if (x < thr_cached) th = L.thr[x];
-                            else if (x < thr_len) th = ch->thr[x];
-                            const uint32_t thi = (uint32_t)(th >> 16);
-                            tlo = (uint32_t)(th & 0xffffu);
-                            accept = rh < thi;
-                            tie = rh == thi;
-                        }
-                    }
-                    if (__ballot(tie) != 0ull && !have_lo) {
-                        const U4 B = philox_stream(ch->seed, (uint32_t)(p >> 3), t, kDomSweepLo,
-                                                   ch->rep, ch->inst);
-                        rl = half_word(B, (uint32_t)(p & 7));
-                        have_lo = true;
-                    }
-                    if (tie) accept = rl < tlo;
-                    const unsigned long long m = __ballot(accept);
-                    if (m == 0ull) break;
-                    const int j = __ffsll((long long)m) - 1;
-                    const uint32_t sbj = (uint32_t)__shfl((int)sb, j) ^ 1u;   // new bit of j
-                    if (lane == j) sb = sbj;
-                    if (lane == 0) L.flips[nf] = (base + j) | (int32_t)(sbj << 31);
-                    ++nf;
-                    const int32_t sj = sbj ? -1 : 1;
-                    if (lane > j) Hp += 2 * sj * (int32_t)L.tile[j * kSkTile + lane];
-                    start = j + 1;
-                }
-                const unsigned long long mask = __ballot(sb != 0u);
-                if (lane == 0) {
-                    // base is a multiple of 64: two whole words
-                    L.bits[base >> 5] = (uint32_t)mask;
-                    if ((base >> 5) + 1 < wn) L.bits[(base >> 5) + 1] = (uint32_t)(mask >> 32);
-                    L.misc[0] = nf;
-                }
-                acc += (lane == 0) ? (uint32_t)nf : 0u;
+            while (x0 > 0 && !((unsigned long long)r < thr_at(L, ch, cached, x0))) --x0;
+            while (x0 + 1 < ch->thr_len && (unsigned long long)r < thr_at(L, ch, cached, x0 + 1)) ++x0;
+            L.xm[slot * 64 + lane] = x0;
+            // coupling tiles (bit-packed, bit 1 = J -1): rows of this block and of
+            // the previous block, columns of this block
+            const int32_t bp = b == 0 ? NB - 1 : b - 1;
+            const int32_t rd = (b << 6) + lane, rp = (bp << 6) + lane;
+            const int32_t w0 = 2 * b, w1 = 2 * b + 1;
+            uint4 tv;
+            tv.x = rd < n ? Jb[(int64_t)rd * wn + w0] : 0u;
+            tv.y = (rd < n && w1 < wn) ? Jb[(int64_t)rd * wn + w1] : 0u;
+            tv.z = rp < n ? Jb[(int64_t)rp * wn + w0] : 0u;
+            tv.w = (rp < n && w1 < wn) ? Jb[(int64_t)rp * wn + w1] : 0u;
+            ((uint4*)L.tile)[slot * 64 + lane] = tv;
+            wave_release();
+            if (lane == 0) st_rel(&L.sync[kPrepared], (int32_t)(g + 1));
+            if (++b == NB) {
+                b = 0;
+                ++s;
             }
-            __syncthreads();
-            const int32_t nf = L.misc[0];
-            for (int32_t f = 0; f < nf; ++f) {
-                const int32_t fv = L.flips[f];
-                const int32_t pf = fv & 0x7fffffff;
-                const int32_t two_s = fv < 0 ? -2 : 2;
-                const int8_t* __restrict__ row = J + (int64_t)pf * n;
-                for (int32_t k = tid; k < n; k += nthr) L.H[k] += two_s * (int32_t)row[k];
-            }
-            __syncthreads();
         }
-        const int64_t tn = t0 + s + 1;
-        if (tn <= t_max && (tn & (tn - 1)) == 0) {
-            const int k = 1 + (63 - __clzll((unsigned long long)tn));
-            for (int32_t w = tid; w < wn; w += nthr) ch->snap[(int64_t)k * wn + w] = L.bits[w];
-            if (tid == 0) L.red[0] = 0;
-            __syncthreads();
-            long long part = 0;
-            for (int32_t i = tid; i < n; i += nthr) {
-                const int32_t si = ((L.bits[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
-                part += (long long)si * L.H[i];
+    } else if (wave == 0) {
+        // ---------------- decider ----------------
+        uint32_t acc = 0;
+        int32_t b = 0, s = 0;
+        for (int64_t g = 0; g < total; ++g) {
+            const int slot = (int)(g & (kRing - 1));
+            wait_ge(L, kPrepared, (int32_t)(g + 1), err);
+            if (g >= 2) wait_ge(L, kApplied, (int32_t)(g - 1), err);
+            const int32_t p = (b << 6) + lane;
+            const bool act = p < n;
+            const int32_t xm = L.xm[slot * 64 + lane];
+            const uint4 tv = ((const uint4*)L.tile)[slot * 64 + lane];
+            int32_t Hp = act ? L.H[p] : 0;
+            uint32_t sb = act ? (L.bits[p >> 5] >> (p & 31)) & 1u : 0u;
+            const uint32_t sh = (uint32_t)lane & 31u;
+            if (g > 0 && NB > 1) {
+                // fields of this block still miss the previous block's flips
+                const int ps = (int)((g - 1) & (kRing - 1));
+                const int32_t nfp = L.nflip[ps];
+                for (int32_t f = 0; f < nfp; ++f) {
+                    const int32_t fv = __builtin_amdgcn_readfirstlane(L.flips[ps * 64 + f]);
+                    const int jf = fv & 63;
+                    const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)tv.z, jf)
+                                                 : (uint32_t)__builtin_amdgcn_readlane((int)tv.w, jf);
+                    const int32_t jv = ((w >> sh) & 1u) ? -1 : 1;
+                    Hp += (fv < 0 ? -2 : 2) * jv;
+                }
             }
-            atomicAdd((unsigned long long*)&L.red[0], (unsigned long long)part);
-            __syncthreads();
-            if (tid == 0) ch->bond[k] = L.red[0] / 2;
-            __syncthreads();
+            int32_t start = 0, nf = 0;
+            for (;;) {
+                const int32_t x = sb ? -Hp : Hp;
+                const bool flip = act && lane >= start && x <= xm;
+                const unsigned long long m = __ballot(flip);
+                if (m == 0ull) break;
+                const int j = __ffsll((long long)m) - 1;
+                const uint32_t nb = (uint32_t)__builtin_amdgcn_readlane((int)sb, j) ^ 1u;   // new bit of j
+                if (lane == j) sb = nb;
+                const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)tv.x, j)
+                                             : (uint32_t)__builtin_amdgcn_readlane((int)tv.y, j);
+                const int32_t jv = ((w >> sh) & 1u) ? -1 : 1;
+                if (lane != j) Hp += (nb ? -2 : 2) * jv;
+                if (lane == 0) L.flips[slot * 64 + nf] = j | (int32_t)(nb << 31);
+                ++nf;
+                start = j + 1;
+            }
+            if (act) L.H[p] = Hp;
+            const unsigned long long mask = __ballot(sb != 0u);
+            if (lane == 0) {
+                L.bits[2 * b] = (uint32_t)mask;
+                if (2 * b + 1 < wn) L.bits[2 * b + 1] = (uint32_t)(mask >> 32);
+                L.nflip[slot] = nf;
+                acc += (uint32_t)nf;
+            }
+            wave_release();
+            if (lane == 0) st_rel(&L.sync[kDecided], (int32_t)(g + 1));
+            if (++b == NB) {
+                b = 0;
+                ++s;
+                const int64_t tn = t0 + s;
+                if (tn <= t_max && (tn & (tn - 1)) == 0) {
+                    const int k = 1 + (63 - __clzll((unsigned long long)tn));
+                    for (int32_t w = lane; w < wn; w += 64) ch->snap[(int64_t)k * wn + w] = L.bits[w];
+                }
+            }
+        }
+        if (lane == 0 && acc) atomicAdd(ch->accepted, (unsigned long long)acc);
+    } else {
+        // ---------------- updaters ----------------
+        const int ut = tid - 128;
+        const int32_t nhalf = (n + 15) >> 4;
+        int32_t bk = 0;
+        for (int64_t k = 0; k < total; ++k) {
+            wait_ge(L, kDecided, (int32_t)(k + 1), err);
+            const int slot = (int)(k & (kRing - 1));
+            const int32_t nf = L.nflip[slot];
+            const bool last = k == total - 1;
+            const int32_t bnext = bk + 1 == NB ? 0 : bk + 1;
+            if (nf > 0) {
+                for (int32_t h = ut; h < nhalf; h += 64 * kUpdWaves) {
+                    const int32_t blk = h >> 2;
+                    if (blk == bk || (!last && blk == bnext)) continue;
+                    const int32_t wi = h >> 1;
+                    const uint32_t shift = 16u * (uint32_t)(h & 1);
+                    int32_t accb[16];
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) accb[c] = 0;
+                    int32_t sum2 = 0;
+                    for (int32_t f = 0; f < nf; ++f) {
+                        const int32_t fv = L.flips[slot * 64 + f];
+                        const int32_t row = (bk << 6) + (fv & 63);
+                        const int32_t s2 = fv < 0 ? -2 : 2;
+                        const uint32_t w = Jb[(int64_t)row * wn + wi] >> shift;
+                        sum2 += s2;
+#pragma unroll
+                        for (int c = 0; c < 16; ++c) accb[c] += (int32_t)((w >> c) & 1u) * s2;
+                    }
+                    // H_c += sum_f 2 s_f J_fc with J = 1 - 2 bit
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) {
+                        const int32_t col = (h << 4) + c;
+                        if (col < n) L.H[col] += sum2 - 2 * accb[c];
+                    }
+                }
+            }
+            wave_release();
+            if (lane == 0) {
+                const int old = __hip_atomic_fetch_add(&L.sync[kDone + slot], 1, __ATOMIC_ACQ_REL,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (old == kUpdWaves - 1) {
+                    L.sync[kDone + slot] = 0;
+                    st_rel(&L.sync[kApplied], (int32_t)(k + 1));
+                }
+            }
+            bk = bnext;
         }
     }
+    __syncthreads();
 
     for (int32_t i = tid; i < n; i += nthr) ch->H[i] = L.H[i];
     for (int32_t w = tid; w < wn; w += nthr) ch->state[w] = L.bits[w];
-    if (tid == 0 && acc) atomicAdd(ch->accepted, (unsigned long long)acc);
 }
 
 // Initial configuration and the t = 0 snapshot of every chain.
@@ -199,23 +325,6 @@ __global__ void sk_init_kernel(const SkChain* __restrict__ chains)
     }
 }
 
-// B(t = 0) = (1/2) sum_i s_i H_i from the freshly computed exact fields.
-__global__ void sk_bond0_kernel(const SkChain* __restrict__ chains)
-{
-    __shared__ long long red;
-    const SkChain* ch = chains + blockIdx.x;
-    if (threadIdx.x == 0) red = 0;
-    __syncthreads();
-    long long part = 0;
-    for (int32_t i = threadIdx.x; i < ch->n; i += blockDim.x) {
-        const int32_t si = ((ch->state[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
-        part += (long long)si * ch->H[i];
-    }
-    atomicAdd((unsigned long long*)&red, (unsigned long long)part);
-    __syncthreads();
-    if (threadIdx.x == 0) ch->bond[0] = red / 2;
-}
-
 // 16 spins (bits, 1 = -1) -> 16 int8 of +-1, zeroed where keep_mask bit is 0.
 __device__ __forceinline__ v4i expand16(uint32_t bits, uint32_t keep_mask)
 {
@@ -232,6 +341,24 @@ __device__ __forceinline__ v4i expand16(uint32_t bits, uint32_t keep_mask)
     return r;
 }
 
+// A operand of v_mfma_i32_16x16x64_i8: 16 bytes of row `row` of J from column k0.
+__device__ __forceinline__ v4i j_bytes(const int8_t* __restrict__ J, int32_t n, int32_t row, int32_t k0)
+{
+    v4i a = {0, 0, 0, 0};
+    if (row >= n) return a;
+    const int8_t* src = J + (int64_t)row * n + k0;
+    if ((n & 15) == 0 && k0 + 16 <= n) {
+        const int4 v = *(const int4*)src;
+        a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+    } else {
+        uint32_t w4[4] = {0, 0, 0, 0};
+        for (int b = 0; b < 16; ++b)
+            if (k0 + b < n) w4[b >> 2] |= (uint32_t)(uint8_t)src[b] << (8 * (b & 3));
+        a[0] = (int)w4[0]; a[1] = (int)w4[1]; a[2] = (int)w4[2]; a[3] = (int)w4[3];
+    }
+    return a;
+}
+
 // Exact fields H = J S for all chains of one sample, by int8 MFMA.
 // Block = 4 wavefronts = 64 rows; grid = (row blocks, samples).
 __global__ void __launch_bounds__(256) sk_recompute_kernel(const SkSample* __restrict__ samples,
@@ -243,34 +370,18 @@ __global__ void __launch_bounds__(256) sk_recompute_kernel(const SkSample* __res
     const int32_t i0 = blockIdx.x * 64 + (threadIdx.x >> 6) * 16;
     if (i0 >= n) return;
     const int lane = threadIdx.x & 63;
-    const int32_t row = i0 + (lane & 15);
     const int kg = lane >> 4;
     const int jc = lane & 15;               // chain column of operand B
     const SkChain* cj = jc < nch ? &chains[sm->chain0 + jc] : nullptr;
-    const int8_t* __restrict__ J = sm->J;
     v4i acc = {0, 0, 0, 0};
-    const bool vec_ok = (n & 15) == 0;
     for (int32_t kc = 0; kc < n; kc += 64) {
         const int32_t k0 = kc + 16 * kg;
-        v4i a = {0, 0, 0, 0};
-        if (row < n) {
-            const int8_t* src = J + (int64_t)row * n + k0;
-            if (vec_ok && k0 + 16 <= n) {
-                const int4 v = *(const int4*)src;
-                a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
-            } else {
-                uint32_t w4[4] = {0, 0, 0, 0};
-                for (int b = 0; b < 16; ++b)
-                    if (k0 + b < n) w4[b >> 2] |= (uint32_t)(uint8_t)src[b] << (8 * (b & 3));
-                a[0] = (int)w4[0]; a[1] = (int)w4[1]; a[2] = (int)w4[2]; a[3] = (int)w4[3];
-            }
-        }
+        const v4i a = j_bytes(sm->J, n, i0 + (lane & 15), k0);
         v4i bv = {0, 0, 0, 0};
         if (cj != nullptr && k0 < n) {
             const uint32_t bits = (cj->state[k0 >> 5] >> (k0 & 31)) & 0xffffu;
             const int32_t valid = min(16, n - k0);
-            const uint32_t keep = valid >= 16 ? 0xffffu : ((1u << valid) - 1u);
-            bv = expand16(bits, keep);
+            bv = expand16(bits, valid >= 16 ? 0xffffu : ((1u << valid) - 1u));
         }
         acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bv, acc, 0, 0, 0);
     }
@@ -285,26 +396,70 @@ __global__ void __launch_bounds__(256) sk_recompute_kernel(const SkSample* __res
     }
 }
 
+// Bond sums of the snapshots: D = J S for the columns (chain r, snapshot k) of
+// one sample by int8 MFMA, then sum_i S_ic D_ic.  Accumulates 2 B into
+// out[chain][k]; grid = (row blocks, column tiles of 16, samples).
+__global__ void __launch_bounds__(256) sk_bond_kernel(const SkSample* __restrict__ samples,
+                                                      const SkChain* __restrict__ chains, int kd,
+                                                      int k_cap, long long* __restrict__ out)
+{
+    const SkSample* sm = samples + blockIdx.z;
+    const int32_t n = sm->n, nch = sm->nch;
+    const int32_t i0 = blockIdx.x * 64 + (threadIdx.x >> 6) * 16;
+    const int32_t ncol = nch * kd;
+    if (i0 >= n || (int32_t)blockIdx.y * 16 >= ncol) return;
+    const int lane = threadIdx.x & 63;
+    const int kg = lane >> 4;
+    const int32_t col = blockIdx.y * 16 + (lane & 15);
+    const bool live = col < ncol;
+    const int32_t cr = live ? col / kd : 0, ck = live ? col - (col / kd) * kd : 0;
+    const SkChain* cj = &chains[sm->chain0 + cr];
+    const uint32_t* snap = cj->snap + (int64_t)ck * cj->words_n;
+    v4i acc = {0, 0, 0, 0};
+    for (int32_t kc = 0; kc < n; kc += 64) {
+        const int32_t k0 = kc + 16 * kg;
+        const v4i a = j_bytes(sm->J, n, i0 + (lane & 15), k0);
+        v4i bv = {0, 0, 0, 0};
+        if (live && k0 < n) {
+            const uint32_t bits = (snap[k0 >> 5] >> (k0 & 31)) & 0xffffu;
+            const int32_t valid = min(16, n - k0);
+            bv = expand16(bits, valid >= 16 ? 0xffffu : ((1u << valid) - 1u));
+        }
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bv, acc, 0, 0, 0);
+    }
+    long long part = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int32_t i = i0 + 4 * kg + r;
+        if (live && i < n) {
+            const int32_t si = ((snap[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+            part += (long long)si * acc[r];
+        }
+    }
+    // lanes l, l+16, l+32, l+48 hold the same column
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    if (live && kg == 0)
+        atomicAdd((unsigned long long*)&out[(int64_t)(sm->chain0 + cr) * k_cap + ck],
+                  (unsigned long long)part);
+}
+
 }  // namespace
 
 size_t sk_lds_bytes(int32_t n)
 {
-    const int32_t wn = (n + 31) / 32;
-    return (((size_t)n * 4 + 15) & ~(size_t)15) + (((size_t)(wn + 2) * 4 + 15) & ~(size_t)15) +
-           (size_t)kSkThrLds * 8 + (size_t)kSkTile * kSkTile + kSkTile * 4 + 16 + 16;
+    const size_t wn = (size_t)(n + 31) / 32;
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    return r16((size_t)n * 4) + r16((wn + 2) * 4) + r16((size_t)kSkThrLds * 8) + r16(kRing * 64 * 4) +
+           r16(kRing * 64 * 16) + r16(kRing * 64 * 4) + r16(kRing * 4) + r16((4 + kRing) * 4);
 }
+
+int sk_threads() { return kSkThreads; }
 
 hipError_t sk_init(const SkChain* chains, int n_chains, int threads, hipStream_t s)
 {
     if (n_chains <= 0) return hipSuccess;
     hipLaunchKernelGGL(sk_init_kernel, dim3(n_chains), dim3(threads), 0, s, chains);
-    return hipGetLastError();
-}
-
-hipError_t sk_bond_t0(const SkChain* chains, int n_chains, hipStream_t s)
-{
-    if (n_chains <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sk_bond0_kernel, dim3(n_chains), dim3(256), 0, s, chains);
     return hipGetLastError();
 }
 
@@ -317,8 +472,17 @@ hipError_t sk_recompute(const SkSample* samples, int n_samples, const SkChain* c
     return hipGetLastError();
 }
 
-hipError_t sk_sweep(const SkChain* chains, int n_chains, int threads, size_t lds_bytes, int64_t t0,
-                    int32_t n_sweeps, int64_t t_max, hipStream_t s)
+hipError_t sk_bond(const SkSample* samples, int n_samples, const SkChain* chains, int max_n, int max_nch,
+                   int k_done, int k_cap, long long* out, hipStream_t s)
+{
+    if (n_samples <= 0 || k_done <= 0) return hipSuccess;
+    dim3 grid((max_n + 63) / 64, (max_nch * k_done + 15) / 16, n_samples);
+    hipLaunchKernelGGL(sk_bond_kernel, grid, dim3(256), 0, s, samples, chains, k_done, k_cap, out);
+    return hipGetLastError();
+}
+
+hipError_t sk_sweep(const SkChain* chains, int n_chains, int, size_t lds_bytes, int64_t t0,
+                    int32_t n_sweeps, int64_t t_max, int* err_flag, hipStream_t s)
 {
     if (n_chains <= 0 || n_sweeps <= 0) return hipSuccess;
     static bool attr_set = false;
@@ -328,8 +492,8 @@ hipError_t sk_sweep(const SkChain* chains, int n_chains, int threads, size_t lds
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(sk_sweep_kernel, dim3(n_chains), dim3(threads), lds_bytes, s, chains, t0,
-                       n_sweeps, t_max);
+    hipLaunchKernelGGL(sk_sweep_kernel, dim3(n_chains), dim3(kSkThreads), lds_bytes, s, chains, t0,
+                       n_sweeps, t_max, err_flag);
     return hipGetLastError();
 }
 

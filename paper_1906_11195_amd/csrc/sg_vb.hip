@@ -44,9 +44,10 @@ struct VbLds {
     uint32_t* tlo;                // [8][64]
     unsigned long long* accs;     // [8]
     uint4* xch;                   // [threads] Philox blocks
+    int32_t* area;                // resident adjacency: row starts, then entries
 };
 
-__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw)
+__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr)
 {
     VbLds L;
     L.sp = smem;
@@ -54,6 +55,7 @@ __device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw)
     L.tlo = L.thi + kVbMaxChains * kVbXMax;
     L.accs = (unsigned long long*)(L.tlo + kVbMaxChains * kVbXMax);
     L.xch = (uint4*)(L.accs + kVbMaxChains);
+    L.area = (int32_t*)(L.xch + nthr);
     return L;
 }
 
@@ -89,29 +91,31 @@ struct Stage {
     uint32_t e[kDMax];
 };
 
-__device__ __forceinline__ void load_rows(const VbUnit* __restrict__ up, const int32_t* __restrict__ cls,
+// `row` and `ent` point to HBM, or to LDS when the adjacency is resident.
+__device__ __forceinline__ void load_rows(const int32_t* __restrict__ row, const int32_t* __restrict__ cls,
                                           const Cursor& c, int lane, Stage& st)
 {
     const int32_t lo = cls[c.k], hi = cls[c.k + 1];
     st.q = (((lo >> 6) + c.j) << 6) + lane;
     const bool act = st.q >= lo && st.q < hi;
-    st.r0 = act ? up->row[st.q] : 0;
-    st.r1 = act ? up->row[st.q + 1] : 0;
+    st.r0 = act ? row[st.q] : 0;
+    st.r1 = act ? row[st.q + 1] : 0;
 }
 
-__device__ __forceinline__ void load_ents(const VbUnit* __restrict__ up, Stage& st)
+__device__ __forceinline__ void load_ents(const uint32_t* __restrict__ ent, Stage& st)
 {
     const int32_t deg = st.r1 - st.r0;
 #pragma unroll
-    for (int d = 0; d < kDMax; ++d) st.e[d] = d < deg ? up->ent[st.r0 + d] : 0u;
+    for (int d = 0; d < kDMax; ++d) st.e[d] = d < deg ? ent[st.r0 + d] : 0u;
 }
 
 // Updates the positions of one chunk for every chain of the unit.
 template <int RPAD>
 __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const VbLds& L,
-                                         const Stage& st, int32_t lo, int32_t hi, uint32_t t,
-                                         int32_t nch, uint64_t key, uint32_t my_rep,
-                                         uint32_t my_inst, uint32_t* acc)
+                                         const uint32_t* __restrict__ ent, const Stage& st,
+                                         int32_t lo, int32_t hi, uint32_t t, int32_t nch,
+                                         uint64_t key, uint32_t my_rep, uint32_t my_inst,
+                                         uint32_t* acc)
 {
     const int tid = threadIdx.x;
     const int32_t q = st.q;
@@ -145,7 +149,7 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
         if (!__any(d < deg)) break;
         if (d < deg) bond(st.e[d]);
     }
-    for (int32_t d = kDMax; d < deg; ++d) bond(up->ent[st.r0 + d]);
+    for (int32_t d = kDMax; d < deg; ++d) bond(ent[st.r0 + d]);
 
     const uint32_t* gx = (const uint32_t*)(L.xch + (tid & ~7));
     const uint32_t hsel = (uint32_t)tid & 7u;
@@ -190,7 +194,7 @@ __device__ void vb_snapshot(const VbUnit* __restrict__ up, const uint32_t* __res
     }
 }
 
-template <int RPAD>
+template <int RPAD, bool RES>
 __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0, int32_t nsw,
                        int64_t t_max)
 {
@@ -198,7 +202,7 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
     const int lane = tid & 63, wave = tid >> 6, W = nthr >> 6;
     const int32_t sw = up->state_words, nch = up->nch, ncls = up->ncls;
     const int32_t* __restrict__ cls = up->cls;
-    const VbLds L = vb_carve(smem, sw);
+    const VbLds L = vb_carve(smem, sw, nthr);
 
     for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = up->state[w];
     for (int i = tid; i < kVbMaxChains * kVbXMax; i += nthr) {
@@ -206,6 +210,17 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
         L.tlo[i] = (&up->thr_lo[0][0])[i];
     }
     if (tid < kVbMaxChains) L.accs[tid] = 0;
+    const int32_t* row = up->row;
+    const uint32_t* ent = up->ent;
+    if (RES) {
+        const int32_t n = up->n;
+        for (int32_t i = tid; i <= n; i += nthr) L.area[i] = up->row[i];
+        uint32_t* re = (uint32_t*)(L.area + n + 1);
+        for (int32_t i = tid; i < up->m2; i += nthr) re[i] = up->ent[i];
+        row = L.area;
+        ent = re;
+        __syncthreads();
+    }
     // chain whose Philox block this lane computes
     const uint64_t key = up->key;
     const int cc = tid & 7;
@@ -218,10 +233,10 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
     Cursor cR{0, 0, wave - W};
     bool haveR = nsw > 0 && cursor_next(cR, W, wave, ncls, cls, nsw);
     if (haveR) {
-        load_rows(up, cls, cR, lane, E);
-        load_ents(up, E);
+        load_rows(row, cls, cR, lane, E);
+        load_ents(ent, E);
         haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
-        if (haveR) load_rows(up, cls, cR, lane, R);
+        if (haveR) load_rows(row, cls, cR, lane, R);
     }
     __syncthreads();
 
@@ -240,11 +255,11 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
                     E.q = R.q;
                     E.r0 = R.r0;
                     E.r1 = R.r1;
-                    load_ents(up, E);
+                    load_ents(ent, E);
                     haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
-                    if (haveR) load_rows(up, cls, cR, lane, R);
+                    if (haveR) load_rows(row, cls, cR, lane, R);
                 }
-                vb_chunk<RPAD>(up, L, cur, lo, hi, t, nch, key, my_rep, my_inst, acc);
+                vb_chunk<RPAD>(up, L, ent, cur, lo, hi, t, nch, key, my_rep, my_inst, acc);
             }
             __syncthreads();
         }
@@ -268,11 +283,20 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
     const VbUnit* up = units + blockIdx.x;
-    switch (up->rpad) {
-        case 1: vb_run<1>(up, smem, t0, nsw, t_max); break;
-        case 2: vb_run<2>(up, smem, t0, nsw, t_max); break;
-        case 4: vb_run<4>(up, smem, t0, nsw, t_max); break;
-        default: vb_run<8>(up, smem, t0, nsw, t_max); break;
+    if (up->resident) {
+        switch (up->rpad) {
+            case 1: vb_run<1, true>(up, smem, t0, nsw, t_max); break;
+            case 2: vb_run<2, true>(up, smem, t0, nsw, t_max); break;
+            case 4: vb_run<4, true>(up, smem, t0, nsw, t_max); break;
+            default: vb_run<8, true>(up, smem, t0, nsw, t_max); break;
+        }
+    } else {
+        switch (up->rpad) {
+            case 1: vb_run<1, false>(up, smem, t0, nsw, t_max); break;
+            case 2: vb_run<2, false>(up, smem, t0, nsw, t_max); break;
+            case 4: vb_run<4, false>(up, smem, t0, nsw, t_max); break;
+            default: vb_run<8, false>(up, smem, t0, nsw, t_max); break;
+        }
     }
 }
 
@@ -316,9 +340,10 @@ __global__ void __launch_bounds__(1024) vb_init_kernel(const VbUnit* __restrict_
 
 }  // namespace
 
-int32_t vb_tile_entries(int threads) { return 6 * threads; }
-
-size_t vb_area_bytes(int threads) { return 0 * (size_t)threads; }
+size_t vb_resident_bytes(int32_t n, int32_t m2)
+{
+    return ((size_t)(n + 1 + m2) * 4 + 15) & ~(size_t)15;
+}
 
 size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads)
 {
