@@ -168,6 +168,11 @@ typedef struct sg_opts {
     int32_t reserved;
 } sg_opts;
 
+/* sg_opts.flags (VB contexts; no effect on any result) */
+#define SG_OPT_AUTOTUNE 1u   /* time candidate workgroup sizes per launch group at create
+                                (on a saved copy of the state, restored afterwards) */
+#define SG_OPT_GRAPH 2u      /* replay each sweep chunk as a captured hipGraph */
+
 #define SG_MEASURE_OBS 1u    /* times, bond, overlap, gram, accepted */
 #define SG_MEASURE_SPINS 2u  /* current spins, vertex order */
 

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libsgmi.so")
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE, SG_ESTATE, SG_EPARITY, SG_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 START_RANDOM, START_ALIGNED, START_GIVEN = 0, 1, 2
 MEASURE_OBS, MEASURE_SPINS = 1, 2
+OPT_AUTOTUNE, OPT_GRAPH = 1, 2
 
 EXPORTS = ("sg_create_vb", "sg_create_sk", "sg_sweep", "sg_measure", "sg_free", "sg_strerror",
            "sg_vb_inspect", "sg_sk_inspect")
@@ -211,11 +212,12 @@ _ALLOC_CB = _ALLOC_FN(_torch_alloc)
 _FREE_CB = _FREE_FN(_torch_free)
 
 
-def _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc):
+def _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags=0):
     o = _Opts()
     o.t_max = int(t_max)
     o.chains_per_unit = int(chains_per_unit)
     o.threads_per_unit = int(threads_per_unit)
+    o.flags = int(flags)
     if torch_alloc:
         o.alloc, o.free = _ALLOC_CB, _FREE_CB
     return o
@@ -263,10 +265,12 @@ def _grid_len(t_max):
 
 
 def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
-                 threads_per_unit: int = 0, torch_alloc: bool = True) -> Context:
+                 threads_per_unit: int = 0, torch_alloc: bool = True, autotune: bool = False,
+                 graph: bool = False) -> Context:
     keep = []
     arr = (_VbDesc * len(descs))(*[_vb_struct(d, keep) for d in descs])
-    o = _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc)
+    flags = (OPT_AUTOTUNE if autotune else 0) | (OPT_GRAPH if graph else 0)
+    o = _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags)
     out = ctypes.c_void_p()
     _check(library().sg_create_vb(ctypes.byref(arr), len(descs), ctypes.byref(o), ctypes.byref(out)),
            "sg_create_vb")

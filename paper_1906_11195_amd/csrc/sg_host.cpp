@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -329,9 +332,24 @@ struct sg_ctx {
     VbUnit* units_d = nullptr;
     int32_t* unit_chain_ids_d = nullptr;
     std::vector<std::pair<int32_t, int32_t>> chain_loc;   // chain -> (unit, slot)
-    int vb_threads = 256;
-    size_t vb_lds = 0, bond_lds = 0;
+    int vb_threads = 64;                  // widest launch group (measurement kernels)
+    size_t bond_lds = 0;
     int64_t updates_per_sweep = 0;
+    // launch groups: units of one workgroup size, one kernel per sweep chunk
+    struct Group {
+        int threads = 64;
+        size_t lds = 0;
+        int32_t first = 0, count = 0;     // range in units_d
+        int64_t updates = 0;              // chain-updates per sweep
+        hipStream_t stream = nullptr;     // own stream for groups after the first
+        hipEvent_t done = nullptr;
+    };
+    std::vector<Group> groups;
+    hipEvent_t fork = nullptr;
+    int64_t* t_dev = nullptr;             // device counter of sweeps done
+    bool use_graph = false;
+    hipStream_t capture_stream = nullptr; // for capturing when the caller uses the null stream
+    std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;   // chunk length -> executable
     // SK
     std::vector<SkChain> sk;
     SkChain* sk_d = nullptr;
@@ -366,11 +384,29 @@ struct sg_ctx {
     }
     void release()
     {
+        for (auto& gx : graphs) (void)hipGraphExecDestroy(gx.second);
+        graphs.clear();
+        for (auto& G : groups) {
+            if (G.stream) (void)hipStreamDestroy(G.stream);
+            if (G.done) (void)hipEventDestroy(G.done);
+            G.stream = nullptr;
+            G.done = nullptr;
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        fork = nullptr;
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        capture_stream = nullptr;
         if (arena) {
             if (alloc && freef) freef(arena, arena_bytes, user);
             else if (!alloc) (void)hipFree(arena);
             arena = nullptr;
         }
+    }
+    void dev_free(void* p, size_t bytes)
+    {
+        if (!p) return;
+        if (alloc && freef) freef(p, bytes, user);
+        else if (!alloc) (void)hipFree(p);
     }
     template <class T>
     T* at(size_t off) { return reinterpret_cast<T*>(static_cast<char*>(arena) + off); }
@@ -408,6 +444,156 @@ void setup_common(sg_ctx* c, const sg_opts* o)
     hipDeviceProp_t prop;
     hip_check(hipGetDeviceProperties(&prop, c->device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) fail(SG_EDEVICE);
+}
+
+// Enqueues `nsw` sweeps of every launch group on stream s: the groups after
+// the first fork onto their own streams and join back; the device sweep
+// counter advances after the join (when `advance`).
+void vb_launch_chunk(sg_ctx* c, int32_t nsw, hipStream_t s, const int64_t* t0p, bool advance)
+{
+    const size_t ng = c->groups.size();
+    if (ng > 1) {
+        hip_check(hipEventRecord(c->fork, s));
+        for (size_t gi = 1; gi < ng; ++gi) hip_check(hipStreamWaitEvent(c->groups[gi].stream, c->fork, 0));
+    }
+    for (size_t gi = 0; gi < ng; ++gi) {
+        const sg_ctx::Group& G = c->groups[gi];
+        hip_check(vb_sweep(c->units_d + G.first, G.count, G.threads, G.lds, t0p, nsw, c->t_max,
+                           gi == 0 ? s : G.stream));
+    }
+    for (size_t gi = 1; gi < ng; ++gi) {
+        hip_check(hipEventRecord(c->groups[gi].done, c->groups[gi].stream));
+        hip_check(hipStreamWaitEvent(s, c->groups[gi].done, 0));
+    }
+    if (advance) hip_check(vb_advance(c->t_dev, nsw, s));
+}
+
+// The sweep chunk of length nsw captured once as a graph (kernels read the
+// device sweep counter, so one executable serves every replay).
+hipGraphExec_t vb_graph_for(sg_ctx* c, int32_t nsw)
+{
+    for (auto& gx : c->graphs)
+        if (gx.first == nsw) return gx.second;
+    if (!c->capture_stream) hip_check(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->capture_stream;
+    hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    try {
+        vb_launch_chunk(c, nsw, cs, c->t_dev, true);
+    } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(cs, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(e);
+    if (c->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(c->graphs.front().second);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.emplace_back(nsw, exec);
+    return exec;
+}
+
+// Autotuner: for every launch group, times candidate workgroup sizes (half,
+// same, double the heuristic's) on a few trial sweeps and keeps the fastest.
+// Trials run at sweep counters >= 2^31, beyond any measurement time, on a
+// saved copy of the spins and counters that is restored afterwards, so tuning
+// changes no result.  Choices are cached per process by group shape.
+struct TuneKey {
+    int threads, nlog, rpad, resident;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(threads, nlog, rpad, resident) < std::tie(o.threads, o.nlog, o.rpad, o.resident);
+    }
+};
+std::map<TuneKey, int> g_tuned;
+std::mutex g_tuned_mu;
+
+void vb_autotune(sg_ctx* c)
+{
+    const size_t lds_cap = 160 * 1024 - 1024;
+    size_t words = 0;
+    for (const auto& U : c->units) words += (size_t)U.state_words;
+    const size_t bytes = words * 4 + (size_t)c->n_chains * 8;
+    char* save = static_cast<char*>(c->dev_alloc(bytes));
+    struct Restore {
+        sg_ctx* c;
+        char* p;
+        size_t bytes;
+        ~Restore() { c->dev_free(p, bytes); }
+    } guard{c, save, bytes};
+    size_t off = 0;
+    for (const auto& U : c->units) {
+        hip_check(hipMemcpy(save + off, U.state, (size_t)U.state_words * 4, hipMemcpyDeviceToDevice));
+        off += (size_t)U.state_words * 4;
+    }
+    hip_check(hipMemcpy(save + off, c->acc_d, (size_t)c->n_chains * 8, hipMemcpyDeviceToDevice));
+    const int64_t trial_t = ((int64_t)1 << 31) + 7;
+    hip_check(hipMemcpy(c->t_dev + 1, &trial_t, 8, hipMemcpyHostToDevice));
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0));
+    hip_check(hipEventCreate(&e1));
+    for (auto& G : c->groups) {
+        int32_t nmax = 0;
+        for (int32_t u = G.first; u < G.first + G.count; ++u) nmax = std::max(nmax, c->units[(size_t)u].n);
+        const VbUnit& U0 = c->units[(size_t)G.first];
+        int nlog = 0;
+        while ((1 << (nlog + 1)) <= nmax) ++nlog;
+        const TuneKey key{G.threads, nlog, U0.rpad, U0.resident};
+        auto lds_for = [&](int th) {
+            size_t l = 0;
+            for (int32_t u = G.first; u < G.first + G.count; ++u) {
+                const VbUnit& U = c->units[(size_t)u];
+                l = std::max(l, vb_lds_bytes(U.n, U.rpad, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
+            }
+            return l;
+        };
+        int best = -1;
+        {
+            std::lock_guard<std::mutex> lk(g_tuned_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) best = it->second;
+        }
+        if (best < 0) {
+            const int32_t nsw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(32, ((int64_t)1 << 25) / std::max<int64_t>(1, G.updates)));
+            float best_ms = 1e30f;
+            for (int th : {G.threads / 2, G.threads, G.threads * 2}) {
+                if (th < 64 || th > 1024 || lds_for(th) > lds_cap) continue;
+                const size_t lds = lds_for(th);
+                hip_check(vb_sweep(c->units_d + G.first, G.count, th, lds, c->t_dev + 1, 1, c->t_max, nullptr));
+                hip_check(hipEventRecord(e0, nullptr));
+                hip_check(vb_sweep(c->units_d + G.first, G.count, th, lds, c->t_dev + 1, nsw, c->t_max, nullptr));
+                hip_check(hipEventRecord(e1, nullptr));
+                hip_check(hipEventSynchronize(e1));
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = th;
+                }
+            }
+            std::lock_guard<std::mutex> lk(g_tuned_mu);
+            g_tuned[key] = best;
+        }
+        if (best > 0) {
+            G.threads = best;
+            G.lds = lds_for(best);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    off = 0;
+    for (const auto& U : c->units) {
+        hip_check(hipMemcpy(U.state, save + off, (size_t)U.state_words * 4, hipMemcpyDeviceToDevice));
+        off += (size_t)U.state_words * 4;
+    }
+    hip_check(hipMemcpy(c->acc_d, save + off, (size_t)c->n_chains * 8, hipMemcpyDeviceToDevice));
+    hip_check(hipDeviceSynchronize());
+    for (const auto& G : c->groups) c->vb_threads = std::max(c->vb_threads, G.threads);
 }
 
 std::vector<uint32_t> pack_given(const int8_t* s0, int64_t n, const std::vector<int32_t>* order)
@@ -484,6 +670,9 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         int32_t group;
         std::vector<int32_t> chains;
         int32_t rpad;
+        int threads = 64;
+        bool resident = false;
+        int64_t work = 0;
     };
     std::vector<UnitPlan> plan;
     for (size_t gi = 0; gi < n_groups; ++gi) {
@@ -502,33 +691,33 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         }
     }
 
-    // workgroup size: wide enough for the largest colour class, small enough
-    // for every unit's LDS
-    int threads = 64;
-    if (o && o->threads_per_unit) {
-        threads = o->threads_per_unit;
-    } else {
-        int32_t maxcls = 0;
-        for (const auto& g : graphs)
-            for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
-        threads = (int)std::min<int32_t>(1024, std::max<int32_t>(64, (maxcls + 63) / 64 * 64));
-        auto fits = [&](int th) {
-            for (const auto& u : plan)
-                if (vb_lds_bytes((int32_t)graphs[(size_t)u.group].n, u.rpad, th) > lds_cap) return false;
-            return true;
-        };
-        while (threads > 64 && !fits(threads)) threads -= 64;
-    }
-    for (const auto& u : plan)
-        if (vb_lds_bytes((int32_t)graphs[(size_t)u.group].n, u.rpad, threads) > lds_cap) fail(SG_ENOTSUP);
-    // small graphs keep their whole adjacency in LDS for the launch
-    std::vector<int32_t> resident(n_groups, 1);
-    for (const auto& u : plan) {
+    // workgroup size per unit: about three 64-position chunks per wavefront in
+    // its largest colour class, reduced until its LDS fits; small graphs keep
+    // their adjacency LDS-resident.  Units of one size form one launch group,
+    // largest work first inside a group (longest-processing-time order).
+    for (auto& u : plan) {
         const VbGraph& g = graphs[(size_t)u.group];
-        if (vb_lds_bytes((int32_t)g.n, u.rpad, threads) + vb_resident_bytes((int32_t)g.n, (int32_t)g.ent.size()) >
-            lds_cap)
-            resident[(size_t)u.group] = 0;
+        const int32_t n = (int32_t)g.n;
+        int th = 64;
+        if (o && o->threads_per_unit) {
+            th = o->threads_per_unit;
+        } else {
+            int32_t maxcls = 0;
+            for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
+            const int32_t chunks = (maxcls + 63) / 64;
+            int waves = 1;
+            while (waves < 16 && waves * 3 < chunks) waves *= 2;
+            th = 64 * waves;
+            while (th > 64 && vb_lds_bytes(n, u.rpad, th) > lds_cap) th /= 2;
+        }
+        if (vb_lds_bytes(n, u.rpad, th) > lds_cap) fail(SG_ENOTSUP);
+        u.threads = th;
+        u.resident = vb_lds_bytes(n, u.rpad, th) + vb_resident_bytes(n, (int32_t)g.ent.size()) <= lds_cap;
+        u.work = (int64_t)n * (int64_t)u.chains.size();
     }
+    std::stable_sort(plan.begin(), plan.end(), [](const UnitPlan& a, const UnitPlan& b) {
+        return a.threads != b.threads ? a.threads > b.threads : a.work > b.work;
+    });
 
     // device layout
     Arena A;
@@ -563,6 +752,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     const size_t off_ovl = A.take((size_t)std::max(1, c->n_pairs) * c->K * 8);
     const size_t off_gram = A.take((size_t)c->n_chains * c->K * c->K * 8);
     const size_t off_acc = A.take((size_t)c->n_chains * 8);
+    const size_t off_t = A.take(16);
 
     c->arena_bytes = A.size;
     c->arena = c->dev_alloc(A.size);
@@ -596,7 +786,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         U.row = c->at<int32_t>(off_row[(size_t)plan[u].group]);
         U.ent = c->at<uint32_t>(off_ent[(size_t)plan[u].group]);
         U.cls = c->at<int32_t>(off_cls[(size_t)plan[u].group]);
-        U.resident = resident[(size_t)plan[u].group];
+        U.resident = plan[u].resident ? 1 : 0;
         U.m2 = (int32_t)g.ent.size();
         // chains of a unit share one graph, hence one seed (graphs are keyed by
         // seed; an explicit edge list belongs to one instance)
@@ -629,12 +819,21 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
             c->chain_loc[(size_t)ch] = {(int32_t)u, k};
         }
         c->units[u] = U;
-        c->vb_lds = std::max(c->vb_lds, vb_lds_bytes(U.n, U.rpad, threads) +
-                                            (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
+        const int th = plan[u].threads;
+        if (c->groups.empty() || c->groups.back().threads != th) {
+            sg_ctx::Group G;
+            G.threads = th;
+            G.first = (int32_t)u;
+            c->groups.push_back(G);
+        }
+        sg_ctx::Group& G = c->groups.back();
+        G.count++;
+        G.updates += g.n * U.nch;
+        G.lds = std::max(G.lds, vb_lds_bytes(U.n, U.rpad, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
+        c->vb_threads = std::max(c->vb_threads, th);
         c->bond_lds = std::max(c->bond_lds, (size_t)(((U.nch * U.words_n + 1) & ~1) * 4 + kVbMaxChains * 8));
         c->updates_per_sweep += g.n * U.nch;
     }
-    c->vb_threads = threads;
     c->order_of_group.resize(n_groups);
     for (size_t gi = 0; gi < n_groups; ++gi) c->order_of_group[gi] = std::move(graphs[gi].order);
 
@@ -663,10 +862,22 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     hip_check(hipMemcpy(c->mc_d, mc.data(), mc.size() * sizeof(MeasureChain), hipMemcpyHostToDevice));
     if (!pairs.empty())
         hip_check(hipMemcpy(c->pairs_d, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
+    c->t_dev = c->at<int64_t>(off_t);
     hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
     hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
+    hip_check(zero_i64((long long*)c->t_dev, 2, nullptr));
     hip_check(vb_init(c->units_d, (int)c->units.size(), 256, 0, nullptr));
+    hip_check(vb_prepare());
+    // every launch group after the first runs on a stream of its own, forked
+    // from and joined back into the caller's stream
+    for (size_t gi = 1; gi < c->groups.size(); ++gi) {
+        hip_check(hipStreamCreateWithFlags(&c->groups[gi].stream, hipStreamNonBlocking));
+        hip_check(hipEventCreateWithFlags(&c->groups[gi].done, hipEventDisableTiming));
+    }
+    hip_check(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    c->use_graph = o && (o->flags & SG_OPT_GRAPH);
     hip_check(hipDeviceSynchronize());
+    if (o && (o->flags & SG_OPT_AUTOTUNE) && !o->threads_per_unit) vb_autotune(c);
 }
 
 void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
@@ -943,8 +1154,10 @@ sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream)
             int64_t left = n_sweeps;
             while (left > 0) {
                 const int64_t chunk = std::min(left, cap);
-                hip_check(vb_sweep(c->units_d, (int)c->units.size(), c->vb_threads, c->vb_lds, c->t_done,
-                                   (int32_t)chunk, c->t_max, s));
+                if (c->use_graph)
+                    hip_check(hipGraphLaunch(vb_graph_for(c, (int32_t)chunk), s));
+                else
+                    vb_launch_chunk(c, (int32_t)chunk, s, c->t_dev, true);
                 c->t_done += chunk;
                 left -= chunk;
             }

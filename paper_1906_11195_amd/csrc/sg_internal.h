@@ -79,8 +79,14 @@ struct MeasureChain {
 
 // ---- launchers (return hipError_t) ----
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t lds_bytes, hipStream_t s);
-hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, int64_t t0,
+// One-time kernel attributes (large dynamic LDS); call before launching or
+// capturing VB sweeps.
+hipError_t vb_prepare();
+// t0p: device counter of sweeps done, read by the kernel; vb_advance adds
+// n_sweeps to it on the stream (after every launch group of a chunk).
+hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, const int64_t* t0p,
                     int32_t n_sweeps, int64_t t_max, hipStream_t s);
+hipError_t vb_advance(int64_t* t, int32_t n_sweeps, hipStream_t s);
 // LDS a unit needs for a launch with `threads` lanes per workgroup, and the
 // extra LDS that keeps its whole adjacency resident.
 size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads);

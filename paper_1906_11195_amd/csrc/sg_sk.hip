@@ -39,17 +39,21 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kRing = 4;            // blocks in flight between the roles
+constexpr int kRing = 6;            // blocks in flight between the roles
+constexpr int kWin = 4;             // previous blocks the decider corrects for itself
+constexpr int kTileWords = 2 + 2 * kWin;   // per lane: own-block row, kWin previous rows
+constexpr int kThrCache = 512;      // threshold entries cached in LDS
 constexpr int kUpdWaves = 4;        // updater wavefronts
 constexpr int kSkThreads = 64 * (2 + kUpdWaves);
 constexpr int kSpinLimit = 1 << 22; // bounded waits: a stuck pipeline aborts
+static_assert(kRing >= kWin + 1, "flip batches must outlive the correction window");
 
 struct SkLds {
     int32_t* H;                 // [n]
     uint32_t* bits;             // [wn + 2]
-    unsigned long long* thr;    // [kSkThrLds]
+    unsigned long long* thr;    // [kThrCache]
     int32_t* xm;                // [kRing][64]
-    uint32_t* tile;             // [kRing][64][4]: diag word 0, 1, prev word 0, 1
+    uint32_t* tile;             // [kRing][64][kTileWords]
     int32_t* flips;             // [kRing][64]: local row | (new spin -1) << 31
     int32_t* nflip;             // [kRing]
     int32_t* sync;              // decided, applied, prepared, abort, done[kRing]
@@ -66,9 +70,9 @@ __device__ __forceinline__ SkLds sk_carve(uint8_t* base, int32_t n, int32_t wn)
     };
     L.H = (int32_t*)take((size_t)n * 4);
     L.bits = (uint32_t*)take((size_t)(wn + 2) * 4);
-    L.thr = (unsigned long long*)take((size_t)kSkThrLds * 8);
+    L.thr = (unsigned long long*)take((size_t)kThrCache * 8);
     L.xm = (int32_t*)take((size_t)kRing * 64 * 4);
-    L.tile = (uint32_t*)take((size_t)kRing * 64 * 16);
+    L.tile = (uint32_t*)take((size_t)kRing * 64 * kTileWords * 4);
     L.flips = (int32_t*)take((size_t)kRing * 64 * 4);
     L.nflip = (int32_t*)take((size_t)kRing * 4);
     L.sync = (int32_t*)take((size_t)(4 + kRing) * 4);
@@ -127,7 +131,7 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
     const SkLds L = sk_carve(sk_smem, n, wn);
-    const int32_t cached = min(ch->thr_len, kSkThrLds);
+    const int32_t cached = min(ch->thr_len, kThrCache);
 
     for (int32_t i = tid; i < n; i += nthr) L.H[i] = ch->H[i];
     for (int32_t w = tid; w < wn + 2; w += nthr) L.bits[w] = w < wn ? ch->state[w] : 0u;
@@ -136,15 +140,18 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
     __syncthreads();
 
     const int32_t NB = (n + 63) >> 6;
+    // correction window: the decider adds the flips of the previous DW blocks
+    // itself; the updaters skip those blocks' columns (DW < NB keeps a block
+    // from correcting for its own earlier visit)
+    const int32_t DW = min(kWin, NB - 1);
     const int64_t total = (int64_t)nsw * NB;
     const uint32_t* __restrict__ Jb = ch->Jb;
 
     if (wave == 1) {
         // ---------------- prep ----------------
-        int32_t b = 0, s = 0;
+        int32_t b = 0, s = 0, slot = 0;
         for (int64_t g = 0; g < total; ++g) {
             if (g >= kRing) wait_ge(L, kDecided, (int32_t)(g - kRing + 1), err);
-            const int slot = (int)(g & (kRing - 1));
             const int32_t p = (b << 6) + lane;
             const uint32_t t = (uint32_t)(t0 + s);
             const U4 A = philox_stream(ch->seed, (uint32_t)p >> 3, t, kDomSweepHi, ch->rep, ch->inst);
@@ -163,19 +170,21 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             while (x0 > 0 && !((unsigned long long)r < thr_at(L, ch, cached, x0))) --x0;
             while (x0 + 1 < ch->thr_len && (unsigned long long)r < thr_at(L, ch, cached, x0 + 1)) ++x0;
             L.xm[slot * 64 + lane] = x0;
-            // coupling tiles (bit-packed, bit 1 = J -1): rows of this block and of
-            // the previous block, columns of this block
-            const int32_t bp = b == 0 ? NB - 1 : b - 1;
-            const int32_t rd = (b << 6) + lane, rp = (bp << 6) + lane;
+            // coupling tiles (bit-packed, bit 1 = J -1), columns of this block:
+            // row 64 b + lane, then rows 64 (b - d) + lane for d = 1..DW
             const int32_t w0 = 2 * b, w1 = 2 * b + 1;
-            uint4 tv;
-            tv.x = rd < n ? Jb[(int64_t)rd * wn + w0] : 0u;
-            tv.y = (rd < n && w1 < wn) ? Jb[(int64_t)rd * wn + w1] : 0u;
-            tv.z = rp < n ? Jb[(int64_t)rp * wn + w0] : 0u;
-            tv.w = (rp < n && w1 < wn) ? Jb[(int64_t)rp * wn + w1] : 0u;
-            ((uint4*)L.tile)[slot * 64 + lane] = tv;
+            uint32_t* tl = L.tile + ((size_t)slot * 64 + lane) * kTileWords;
+#pragma unroll
+            for (int d = 0; d <= kWin; ++d) {
+                if (d > DW) break;
+                const int32_t bb = b - d < 0 ? b - d + NB : b - d;
+                const int32_t rr = (bb << 6) + lane;
+                tl[2 * d] = rr < n ? Jb[(int64_t)rr * wn + w0] : 0u;
+                tl[2 * d + 1] = (rr < n && w1 < wn) ? Jb[(int64_t)rr * wn + w1] : 0u;
+            }
             wave_release();
             if (lane == 0) st_rel(&L.sync[kPrepared], (int32_t)(g + 1));
+            if (++slot == kRing) slot = 0;
             if (++b == NB) {
                 b = 0;
                 ++s;
@@ -184,27 +193,31 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
     } else if (wave == 0) {
         // ---------------- decider ----------------
         uint32_t acc = 0;
-        int32_t b = 0, s = 0;
+        int32_t b = 0, s = 0, slot = 0;
         for (int64_t g = 0; g < total; ++g) {
-            const int slot = (int)(g & (kRing - 1));
             wait_ge(L, kPrepared, (int32_t)(g + 1), err);
-            if (g >= 2) wait_ge(L, kApplied, (int32_t)(g - 1), err);
+            if (g > DW) wait_ge(L, kApplied, (int32_t)(g - DW), err);
             const int32_t p = (b << 6) + lane;
             const bool act = p < n;
             const int32_t xm = L.xm[slot * 64 + lane];
-            const uint4 tv = ((const uint4*)L.tile)[slot * 64 + lane];
+            const uint32_t* tl = L.tile + ((size_t)slot * 64 + lane) * kTileWords;
+            const uint32_t d0 = tl[0], d1 = tl[1];
             int32_t Hp = act ? L.H[p] : 0;
             uint32_t sb = act ? (L.bits[p >> 5] >> (p & 31)) & 1u : 0u;
             const uint32_t sh = (uint32_t)lane & 31u;
-            if (g > 0 && NB > 1) {
-                // fields of this block still miss the previous block's flips
-                const int ps = (int)((g - 1) & (kRing - 1));
+            // this block's fields still miss the flips of the previous DW blocks
+#pragma unroll
+            for (int d = 1; d <= kWin; ++d) {
+                if (d > DW || g - d < 0) break;
+                const uint32_t e0 = tl[2 * d], e1 = tl[2 * d + 1];
+                int ps = slot - d;
+                if (ps < 0) ps += kRing;
                 const int32_t nfp = L.nflip[ps];
                 for (int32_t f = 0; f < nfp; ++f) {
                     const int32_t fv = __builtin_amdgcn_readfirstlane(L.flips[ps * 64 + f]);
                     const int jf = fv & 63;
-                    const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)tv.z, jf)
-                                                 : (uint32_t)__builtin_amdgcn_readlane((int)tv.w, jf);
+                    const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)e0, jf)
+                                                 : (uint32_t)__builtin_amdgcn_readlane((int)e1, jf);
                     const int32_t jv = ((w >> sh) & 1u) ? -1 : 1;
                     Hp += (fv < 0 ? -2 : 2) * jv;
                 }
@@ -218,8 +231,8 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                 const int j = __ffsll((long long)m) - 1;
                 const uint32_t nb = (uint32_t)__builtin_amdgcn_readlane((int)sb, j) ^ 1u;   // new bit of j
                 if (lane == j) sb = nb;
-                const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)tv.x, j)
-                                             : (uint32_t)__builtin_amdgcn_readlane((int)tv.y, j);
+                const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)d0, j)
+                                             : (uint32_t)__builtin_amdgcn_readlane((int)d1, j);
                 const int32_t jv = ((w >> sh) & 1u) ? -1 : 1;
                 if (lane != j) Hp += (nb ? -2 : 2) * jv;
                 if (lane == 0) L.flips[slot * 64 + nf] = j | (int32_t)(nb << 31);
@@ -236,6 +249,7 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             }
             wave_release();
             if (lane == 0) st_rel(&L.sync[kDecided], (int32_t)(g + 1));
+            if (++slot == kRing) slot = 0;
             if (++b == NB) {
                 b = 0;
                 ++s;
@@ -251,31 +265,42 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         // ---------------- updaters ----------------
         const int ut = tid - 128;
         const int32_t nhalf = (n + 15) >> 4;
-        int32_t bk = 0;
+        int32_t bk = 0, slot = 0;
         for (int64_t k = 0; k < total; ++k) {
             wait_ge(L, kDecided, (int32_t)(k + 1), err);
-            const int slot = (int)(k & (kRing - 1));
             const int32_t nf = L.nflip[slot];
-            const bool last = k == total - 1;
-            const int32_t bnext = bk + 1 == NB ? 0 : bk + 1;
+            // blocks bk + d (1 <= d <= DW) decided later in this launch get
+            // this batch from the decider's correction
+            const int32_t dskip = (int32_t)min((int64_t)DW, total - 1 - k);
             if (nf > 0) {
                 for (int32_t h = ut; h < nhalf; h += 64 * kUpdWaves) {
                     const int32_t blk = h >> 2;
-                    if (blk == bk || (!last && blk == bnext)) continue;
+                    int32_t dist = blk - bk;
+                    if (dist < 0) dist += NB;
+                    if (dist <= dskip) continue;   // dist 0: the flipped block itself
                     const int32_t wi = h >> 1;
                     const uint32_t shift = 16u * (uint32_t)(h & 1);
                     int32_t accb[16];
 #pragma unroll
                     for (int c = 0; c < 16; ++c) accb[c] = 0;
                     int32_t sum2 = 0;
-                    for (int32_t f = 0; f < nf; ++f) {
-                        const int32_t fv = L.flips[slot * 64 + f];
-                        const int32_t row = (bk << 6) + (fv & 63);
-                        const int32_t s2 = fv < 0 ? -2 : 2;
-                        const uint32_t w = Jb[(int64_t)row * wn + wi] >> shift;
-                        sum2 += s2;
+                    for (int32_t f0 = 0; f0 < nf; f0 += 8) {
+                        // eight independent row loads in flight
+                        uint32_t wv[8];
+                        int32_t s2v[8];
 #pragma unroll
-                        for (int c = 0; c < 16; ++c) accb[c] += (int32_t)((w >> c) & 1u) * s2;
+                        for (int i = 0; i < 8; ++i) {
+                            const bool live = f0 + i < nf;
+                            const int32_t fv = live ? L.flips[slot * 64 + f0 + i] : 0;
+                            s2v[i] = live ? (fv < 0 ? -2 : 2) : 0;
+                            wv[i] = live ? Jb[(int64_t)((bk << 6) + (fv & 63)) * wn + wi] >> shift : 0u;
+                        }
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            sum2 += s2v[i];
+#pragma unroll
+                            for (int c = 0; c < 16; ++c) accb[c] += (int32_t)((wv[i] >> c) & 1u) * s2v[i];
+                        }
                     }
                     // H_c += sum_f 2 s_f J_fc with J = 1 - 2 bit
 #pragma unroll
@@ -294,7 +319,8 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                     st_rel(&L.sync[kApplied], (int32_t)(k + 1));
                 }
             }
-            bk = bnext;
+            if (++slot == kRing) slot = 0;
+            bk = bk + 1 == NB ? 0 : bk + 1;
         }
     }
     __syncthreads();
@@ -450,8 +476,9 @@ size_t sk_lds_bytes(int32_t n)
 {
     const size_t wn = (size_t)(n + 31) / 32;
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
-    return r16((size_t)n * 4) + r16((wn + 2) * 4) + r16((size_t)kSkThrLds * 8) + r16(kRing * 64 * 4) +
-           r16(kRing * 64 * 16) + r16(kRing * 64 * 4) + r16(kRing * 4) + r16((4 + kRing) * 4);
+    return r16((size_t)n * 4) + r16((wn + 2) * 4) + r16((size_t)kThrCache * 8) + r16(kRing * 64 * 4) +
+           r16((size_t)kRing * 64 * kTileWords * 4) + r16(kRing * 64 * 4) + r16(kRing * 4) +
+           r16((4 + kRing) * 4);
 }
 
 int sk_threads() { return kSkThreads; }

@@ -278,11 +278,16 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
     if (tid < nch) atomicAdd(up->accepted[tid], L.accs[tid]);
 }
 
+// t0p: device-resident number of sweeps done before this launch (read once;
+// the counter is advanced by vb_advance_kernel after every launch group), so
+// a captured graph of the sweep loop can be replayed unchanged.
 __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict__ units,
-                                                        int64_t t0, int32_t nsw, int64_t t_max)
+                                                        const int64_t* __restrict__ t0p,
+                                                        int32_t nsw, int64_t t_max)
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
     const VbUnit* up = units + blockIdx.x;
+    const int64_t t0 = *t0p;
     if (up->resident) {
         switch (up->rpad) {
             case 1: vb_run<1, true>(up, smem, t0, nsw, t_max); break;
@@ -298,6 +303,11 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
             default: vb_run<8, false>(up, smem, t0, nsw, t_max); break;
         }
     }
+}
+
+__global__ void vb_advance_kernel(int64_t* t, int32_t nsw)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *t += nsw;
 }
 
 // Initial configurations and the t = 0 snapshot.
@@ -359,10 +369,8 @@ hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStr
     return hipGetLastError();
 }
 
-hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, int64_t t0,
-                    int32_t n_sweeps, int64_t t_max, hipStream_t s)
+hipError_t vb_prepare()
 {
-    if (n_units <= 0 || n_sweeps <= 0) return hipSuccess;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)vb_sweep_kernel,
@@ -370,8 +378,21 @@ hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_by
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(vb_sweep_kernel, dim3(n_units), dim3(threads), lds_bytes, s, units, t0,
+    return hipSuccess;
+}
+
+hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, const int64_t* t0p,
+                    int32_t n_sweeps, int64_t t_max, hipStream_t s)
+{
+    if (n_units <= 0 || n_sweeps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(vb_sweep_kernel, dim3(n_units), dim3(threads), lds_bytes, s, units, t0p,
                        n_sweeps, t_max);
+    return hipGetLastError();
+}
+
+hipError_t vb_advance(int64_t* t, int32_t n_sweeps, hipStream_t s)
+{
+    hipLaunchKernelGGL(vb_advance_kernel, dim3(1), dim3(64), 0, s, t, n_sweeps);
     return hipGetLastError();
 }
 
