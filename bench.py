@@ -156,6 +156,49 @@ def run_sk(args, torch, sg, workloads):
                 accepted_fraction=float(res["accepted"].sum() - a0) / upd, sweeps=args.sk_sweeps)
 
 
+def run_uneven(args, torch, sg, workloads):
+    """Uneven batch: 1024 VB instances, N log-uniform in [2^10, 2^20], 2 replicas,
+    autotuned launch groups, graph-replayed sweep chunks; a steady window."""
+    descs = workloads.vb_uneven()
+    t0 = time.perf_counter()
+    ctx = sg.sg_create_vb(descs, t_max=workloads.VB_UNEVEN_SWEEPS, autotune=True, graph=True)
+    create_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    sg.sg_sweep(ctx, 16, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sg.sg_sweep(ctx, args.uneven_sweeps, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sg.sg_free(ctx)
+    upd = sum(d.n for d in descs) * 2 * args.uneven_sweeps
+    return dict(workload="VB uneven: 1024 instances, N log-uniform in [2^10, 2^20], c=4, T in {0.6,0.8,1.0}, "
+                         "2 replicas; sweeps 16..%d, autotuned, hipGraph" % (16 + args.uneven_sweeps),
+                updates_per_ns=upd / (el * 1e9), create_s=round(create_s, 2))
+
+
+def run_serving(args, torch, sg, workloads):
+    """Serving: Poisson arrivals, 70% VB (N in [2^12, 2^20]) / 30% SK (N in
+    [512, 8192]), T ~ U[0.5, 0.9]; run lengths reduced to 2^8..2^10 sweeps so
+    that the leg fits the benchmark's time budget."""
+    from paper_1906_11195_amd import serving
+    reqs = workloads.serving_requests(args.serve_requests, rate=200.0)
+    rng_len = [256, 512, 1024]
+    for i, r in enumerate(reqs):
+        r.sweeps = rng_len[i % 3]
+    server = serving.AgingServer(hbm_budget=64 << 30, max_active=64, chunk_sweeps=256, n_streams=4,
+                                 flags=sg.MEASURE_OBS)
+    t0 = time.perf_counter()
+    results = server.run(reqs, max_wall=120.0)
+    el = time.perf_counter() - t0
+    st = serving.latency_stats(results)
+    upd = sum(2 * r.n * r.sweeps for r in results)
+    st.update(workload="serving: %d Poisson requests at 200/s, 70%% VB N in [2^12,2^20], 30%% SK N in "
+                       "[512,8192], T~U[0.5,0.9], 256..1024 sweeps" % len(reqs),
+              updates_per_ns=upd / (el * 1e9), wall_s=round(el, 2))
+    return st
+
+
 def run_cpu_baseline(args, workloads):
     """The oracle, as it stands, on a bounded sample of the same workload:
     `threads` instances of the batched configuration (N = 65536, 2 replicas)
@@ -204,6 +247,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-vb", action="store_true")
+    ap.add_argument("--uneven-sweeps", type=int, default=128)
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -236,12 +281,16 @@ def main():
     sg.library()
     vb = run_vb_batched(args, torch, sg, workloads)
     log("VB batched: %.1f updates/ns" % vb["value"])
-    plain = sk = None
+    plain = sk = uneven = serve = None
     if not args.only_vb:
         plain = run_vb_plain(args, torch, sg, workloads)
         log("VB plain: p50 %.2f ms" % plain["p50_ms"])
         sk = run_sk(args, torch, sg, workloads)
         log("SK: %.2f updates/ns" % sk["updates_per_ns"])
+        uneven = run_uneven(args, torch, sg, workloads)
+        log("VB uneven: %.1f updates/ns" % uneven["updates_per_ns"])
+        serve = run_serving(args, torch, sg, workloads)
+        log("serving: p50 %.1f ms, p99 %.1f ms" % (serve.get("p50_ms", 0), serve.get("p99_ms", 0)))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(args, workloads)
@@ -274,6 +323,8 @@ def main():
         "cpu_baseline": cpu,
         "plain": plain,
         "sk": sk,
+        "uneven": uneven,
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -7,6 +7,17 @@
 
 namespace sg {
 
+// Device pointers stored in descriptors are generic; re-qualifying them as
+// global memory lets the compiler emit global/scalar loads, which wait only on
+// their own counters, instead of flat loads, which wait on every outstanding
+// load and LDS access.
+#define SG_G __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ SG_G T* gl(T* p)
+{
+    return (SG_G T*)p;
+}
+
 constexpr int kVbMaxChains = 8;    // chains per VB work unit
 constexpr int kVbXMax = 64;        // threshold table length (max degree 63)
 constexpr int kMaxGrid = 32;       // grid times {0} U {2^k <= t_max}, t_max < 2^31

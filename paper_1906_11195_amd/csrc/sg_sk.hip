@@ -39,8 +39,15 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kRing = 6;            // blocks in flight between the roles
-constexpr int kWin = 4;             // previous blocks the decider corrects for itself
+// Pipeline depth (compile-time tuning parameters).
+#ifndef SG_SK_RING
+#define SG_SK_RING 4
+#endif
+#ifndef SG_SK_WIN
+#define SG_SK_WIN 1
+#endif
+constexpr int kRing = SG_SK_RING;   // blocks in flight between the roles
+constexpr int kWin = SG_SK_WIN;     // previous blocks the decider corrects for itself
 constexpr int kTileWords = 2 + 2 * kWin;   // per lane: own-block row, kWin previous rows
 constexpr int kThrCache = 512;      // threshold entries cached in LDS
 constexpr int kUpdWaves = 4;        // updater wavefronts
@@ -118,7 +125,7 @@ __device__ __forceinline__ unsigned long long thr_at(const SkLds& L, const SkCha
                                                       int32_t cached, int32_t x)
 {
     if (x >= ch->thr_len) return 0ull;
-    return x < cached ? L.thr[x] : ch->thr[x];
+    return x < cached ? L.thr[x] : gl(ch->thr)[x];
 }
 
 __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __restrict__ chains,
@@ -126,16 +133,16 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                                                               int64_t t_max, int* err)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t sk_smem[];
-    const SkChain* ch = chains + blockIdx.x;
+    const SkChain* ch = (const SkChain*)(gl(chains) + blockIdx.x);
     const int32_t n = ch->n, wn = ch->words_n;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const SkLds L = sk_carve(sk_smem, n, wn);
     const int32_t cached = min(ch->thr_len, kThrCache);
 
-    for (int32_t i = tid; i < n; i += nthr) L.H[i] = ch->H[i];
-    for (int32_t w = tid; w < wn + 2; w += nthr) L.bits[w] = w < wn ? ch->state[w] : 0u;
-    for (int32_t x = tid; x < cached; x += nthr) L.thr[x] = ch->thr[x];
+    for (int32_t i = tid; i < n; i += nthr) L.H[i] = gl(ch->H)[i];
+    for (int32_t w = tid; w < wn + 2; w += nthr) L.bits[w] = w < wn ? gl(ch->state)[w] : 0u;
+    for (int32_t x = tid; x < cached; x += nthr) L.thr[x] = gl(ch->thr)[x];
     if (tid < 4 + kRing) L.sync[tid] = 0;
     __syncthreads();
 
@@ -145,7 +152,7 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
     // from correcting for its own earlier visit)
     const int32_t DW = min(kWin, NB - 1);
     const int64_t total = (int64_t)nsw * NB;
-    const uint32_t* __restrict__ Jb = ch->Jb;
+    const SG_G uint32_t* __restrict__ Jb = gl(ch->Jb);
 
     if (wave == 1) {
         // ---------------- prep ----------------
@@ -256,7 +263,7 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                 const int64_t tn = t0 + s;
                 if (tn <= t_max && (tn & (tn - 1)) == 0) {
                     const int k = 1 + (63 - __clzll((unsigned long long)tn));
-                    for (int32_t w = lane; w < wn; w += 64) ch->snap[(int64_t)k * wn + w] = L.bits[w];
+                    for (int32_t w = lane; w < wn; w += 64) gl(ch->snap)[(int64_t)k * wn + w] = L.bits[w];
                 }
             }
         }
@@ -325,8 +332,8 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
     }
     __syncthreads();
 
-    for (int32_t i = tid; i < n; i += nthr) ch->H[i] = L.H[i];
-    for (int32_t w = tid; w < wn; w += nthr) ch->state[w] = L.bits[w];
+    for (int32_t i = tid; i < n; i += nthr) gl(ch->H)[i] = L.H[i];
+    for (int32_t w = tid; w < wn; w += nthr) gl(ch->state)[w] = L.bits[w];
 }
 
 // Initial configuration and the t = 0 snapshot of every chain.

@@ -65,15 +65,16 @@ struct Cursor {
     int32_t s, k, j;
 };
 
-__device__ __forceinline__ int32_t n_chunks(const int32_t* __restrict__ cls, int32_t k)
+template <class PC>
+__device__ __forceinline__ int32_t n_chunks(PC cls, int32_t k)
 {
     const int32_t lo = cls[k], hi = cls[k + 1];
     return hi > lo ? ((hi - 1) >> 6) - (lo >> 6) + 1 : 0;
 }
 
 // Moves to the next chunk owned by wavefront `wave`; false past the launch.
-__device__ __forceinline__ bool cursor_next(Cursor& c, int W, int wave, int32_t ncls,
-                                            const int32_t* __restrict__ cls, int32_t nsw)
+template <class PC>
+__device__ __forceinline__ bool cursor_next(Cursor& c, int W, int wave, int32_t ncls, PC cls, int32_t nsw)
 {
     c.j += W;
     for (;;) {
@@ -92,8 +93,8 @@ struct Stage {
 };
 
 // `row` and `ent` point to HBM, or to LDS when the adjacency is resident.
-__device__ __forceinline__ void load_rows(const int32_t* __restrict__ row, const int32_t* __restrict__ cls,
-                                          const Cursor& c, int lane, Stage& st)
+template <class PR, class PC>
+__device__ __forceinline__ void load_rows(PR row, PC cls, const Cursor& c, int lane, Stage& st)
 {
     const int32_t lo = cls[c.k], hi = cls[c.k + 1];
     st.q = (((lo >> 6) + c.j) << 6) + lane;
@@ -102,7 +103,8 @@ __device__ __forceinline__ void load_rows(const int32_t* __restrict__ row, const
     st.r1 = act ? row[st.q + 1] : 0;
 }
 
-__device__ __forceinline__ void load_ents(const uint32_t* __restrict__ ent, Stage& st)
+template <class PE>
+__device__ __forceinline__ void load_ents(PE ent, Stage& st)
 {
     const int32_t deg = st.r1 - st.r0;
 #pragma unroll
@@ -110,9 +112,8 @@ __device__ __forceinline__ void load_ents(const uint32_t* __restrict__ ent, Stag
 }
 
 // Updates the positions of one chunk for every chain of the unit.
-template <int RPAD>
-__device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const VbLds& L,
-                                         const uint32_t* __restrict__ ent, const Stage& st,
+template <int RPAD, class PE>
+__device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const VbLds& L, PE ent, const Stage& st,
                                          int32_t lo, int32_t hi, uint32_t t, int32_t nch,
                                          uint64_t key, uint32_t my_rep, uint32_t my_inst,
                                          uint32_t* acc)
@@ -190,37 +191,58 @@ __device__ void vb_snapshot(const VbUnit* __restrict__ up, const uint32_t* __res
             const uint32_t b = (uint32_t)(32 * w + i) * RPAD + (uint32_t)c;
             bits |= ((sp[b >> 5] >> (b & 31u)) & 1u) << i;
         }
-        up->snap[c][(int64_t)k * wn + w] = bits;
+        gl(up->snap[c])[(int64_t)k * wn + w] = bits;
     }
 }
+
+template <int RPAD, class PR, class PE, class PC>
+__device__ void vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
+                        int32_t nsw, int64_t t_max, int lane, int wave, int W);
 
 template <int RPAD, bool RES>
 __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0, int32_t nsw,
                        int64_t t_max)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, W = nthr >> 6;
+    // wave index made explicitly wave-uniform: the chunk cursor then lives in
+    // scalar registers and class bounds come from scalar loads
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), W = nthr >> 6;
     const int32_t sw = up->state_words, nch = up->nch, ncls = up->ncls;
-    const int32_t* __restrict__ cls = up->cls;
+    const SG_G int32_t* __restrict__ cls = gl(up->cls);
     const VbLds L = vb_carve(smem, sw, nthr);
 
-    for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = up->state[w];
+    const SG_G uint32_t* gstate = gl(up->state);
+    for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = gstate[w];
     for (int i = tid; i < kVbMaxChains * kVbXMax; i += nthr) {
         L.thi[i] = (&up->thr_hi[0][0])[i];
         L.tlo[i] = (&up->thr_lo[0][0])[i];
     }
     if (tid < kVbMaxChains) L.accs[tid] = 0;
-    const int32_t* row = up->row;
-    const uint32_t* ent = up->ent;
     if (RES) {
         const int32_t n = up->n;
-        for (int32_t i = tid; i <= n; i += nthr) L.area[i] = up->row[i];
+        const SG_G int32_t* grow = gl(up->row);
+        const SG_G uint32_t* gent = gl(up->ent);
+        for (int32_t i = tid; i <= n; i += nthr) L.area[i] = grow[i];
         uint32_t* re = (uint32_t*)(L.area + n + 1);
-        for (int32_t i = tid; i < up->m2; i += nthr) re[i] = up->ent[i];
-        row = L.area;
-        ent = re;
+        for (int32_t i = tid; i < up->m2; i += nthr) re[i] = gent[i];
         __syncthreads();
+        vb_loop<RPAD>(up, L, (const int32_t*)L.area, (const uint32_t*)(L.area + n + 1), cls, t0, nsw,
+                      t_max, lane, wave, W);
+    } else {
+        vb_loop<RPAD>(up, L, gl(up->row), gl(up->ent), cls, t0, nsw, t_max, lane, wave, W);
     }
+    for (int32_t w = tid; w < sw; w += nthr) gl(up->state)[w] = L.sp[w];
+    __syncthreads();
+    if (tid < nch) atomicAdd(up->accepted[tid], L.accs[tid]);
+}
+
+// The sweep loop of one unit, for adjacency pointers in HBM or in LDS.
+template <int RPAD, class PR, class PE, class PC>
+__device__ void vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
+                        int32_t nsw, int64_t t_max, int lane, int wave, int W)
+{
+    const int tid = threadIdx.x;
+    const int32_t nch = up->nch, ncls = up->ncls;
     // chain whose Philox block this lane computes
     const uint64_t key = up->key;
     const int cc = tid & 7;
@@ -269,13 +291,9 @@ __device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0
             __syncthreads();
         }
     }
-
-    for (int32_t w = tid; w < sw; w += nthr) up->state[w] = L.sp[w];
 #pragma unroll
     for (int c = 0; c < RPAD; ++c)
         if (c < nch && acc[c]) atomicAdd(&L.accs[c], (unsigned long long)acc[c]);
-    __syncthreads();
-    if (tid < nch) atomicAdd(up->accepted[tid], L.accs[tid]);
 }
 
 // t0p: device-resident number of sweeps done before this launch (read once;
@@ -286,8 +304,8 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
                                                         int32_t nsw, int64_t t_max)
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
-    const VbUnit* up = units + blockIdx.x;
-    const int64_t t0 = *t0p;
+    const VbUnit* up = (const VbUnit*)(gl(units) + blockIdx.x);
+    const int64_t t0 = *gl(t0p);
     if (up->resident) {
         switch (up->rpad) {
             case 1: vb_run<1, true>(up, smem, t0, nsw, t_max); break;
