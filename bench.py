@@ -16,6 +16,7 @@ and the CPU oracle timed on the host's cores on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -61,6 +62,38 @@ def percentile(xs, q):
     f = math.floor(k)
     c = min(f + 1, len(xs) - 1)
     return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+PROFILE_VB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                          "vb_sweep_kernel_vb_batched_n65536.md")
+VB_KERNEL_SOURCES = ("sg_vb.hip", "sg_internal.h", "sg_philox.h")
+
+
+def vb_kernel_digest() -> str:
+    """First 16 hex digits of SHA-256 over the VB sweep kernel's sources."""
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1906_11195_amd", "csrc")
+    for f in VB_KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(sweeps_per_launch: float):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE passes
+    (already scaled by the copy-kernel calibration), or None when the kernel
+    sources have changed since the counters were taken."""
+    try:
+        with open(PROFILE_VB) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines()
+                      if line.startswith("traffic_") and ": " in line)
+    except OSError:
+        return None
+    if kv.get("traffic_kernel_digest", "").strip() != vb_kernel_digest():
+        return None
+    fetch = float(kv["traffic_fetch_kib_per_sweep"]) * 1024.0 * sweeps_per_launch
+    write = float(kv["traffic_write_kib_per_launch"]) * 1024.0
+    return int(fetch + write)
 
 
 def run_vb_batched(args, torch, sg, workloads):
@@ -113,7 +146,8 @@ def run_vb_batched(args, torch, sg, workloads):
         sweep_kernel_updates_per_ns=updates / (sweep_ms * 1e6),
         accepted_per_ns=float(res["accepted"].sum() - accepted0) / (elapsed * 1e9) if accepted0 is not None else None,
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                      frac=round(achieved / HBM_PEAK_GBS, 4),
+                      traffic=profiled_traffic(S / launches_per_step), traffic_unit="bytes per launch",
                       kernel="vb_sweep_kernel", launch_ms=round(launch_ms, 4),
                       bytes_per_launch=int(launch_bytes), bytes_per_update=round(bytes_per_sweep / n_total, 3)),
         ms_per_step=elapsed * 1e3 / args.steps, t_done=res["t_done"])
