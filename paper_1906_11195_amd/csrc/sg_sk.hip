@@ -50,7 +50,10 @@ constexpr int kRing = SG_SK_RING;   // blocks in flight between the roles
 constexpr int kWin = SG_SK_WIN;     // previous blocks the decider corrects for itself
 constexpr int kTileWords = 2 + 2 * kWin;   // per lane: own-block row, kWin previous rows
 constexpr int kThrCache = 512;      // threshold entries cached in LDS
-constexpr int kUpdWaves = 4;        // updater wavefronts
+#ifndef SG_SK_UPD
+#define SG_SK_UPD 4
+#endif
+constexpr int kUpdWaves = SG_SK_UPD;   // updater wavefronts
 constexpr int kSkThreads = 64 * (2 + kUpdWaves);
 constexpr int kSpinLimit = 1 << 22; // bounded waits: a stuck pipeline aborts
 static_assert(kRing >= kWin + 1, "flip batches must outlive the correction window");
@@ -64,6 +67,7 @@ struct SkLds {
     int32_t* flips;             // [kRing][64]: local row | (new spin -1) << 31
     int32_t* nflip;             // [kRing]
     int32_t* sync;              // decided, applied, prepared, abort, done[kRing]
+    uint4* pr;                  // [64] Philox blocks of the prep's current 4 spin blocks
 };
 
 __device__ __forceinline__ SkLds sk_carve(uint8_t* base, int32_t n, int32_t wn)
@@ -83,6 +87,7 @@ __device__ __forceinline__ SkLds sk_carve(uint8_t* base, int32_t n, int32_t wn)
     L.flips = (int32_t*)take((size_t)kRing * 64 * 4);
     L.nflip = (int32_t*)take((size_t)kRing * 4);
     L.sync = (int32_t*)take((size_t)(4 + kRing) * 4);
+    L.pr = (uint4*)take(64 * 16);
     return L;
 }
 
@@ -113,6 +118,13 @@ __device__ __forceinline__ void wait_ge(const SkLds& L, int32_t idx, int32_t tar
             return;
         }
     }
+}
+
+__device__ __forceinline__ void wave_sync_sk()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ void wave_release()
@@ -156,14 +168,49 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
 
     if (wave == 1) {
         // ---------------- prep ----------------
+        // coupling tiles (bit-packed, bit 1 = J -1), columns of block b: row
+        // 64 b + lane, then rows 64 (b - d) + lane for d = 1..DW; the tiles of
+        // the next block are loaded while this block's uniforms are drawn
+        uint32_t tw[2 * (kWin + 1)];
+        auto load_tiles = [&](int32_t bq) {
+            const int32_t w0 = 2 * bq, w1 = 2 * bq + 1;
+#pragma unroll
+            for (int d = 0; d <= kWin; ++d) {
+                const int32_t bb = bq - d < 0 ? bq - d + NB : bq - d;
+                const int32_t rr = (bb << 6) + lane;
+                const bool live = d <= DW && rr < n;
+                tw[2 * d] = live ? Jb[(int64_t)rr * wn + w0] : 0u;
+                tw[2 * d + 1] = (live && w1 < wn) ? Jb[(int64_t)rr * wn + w1] : 0u;
+            }
+        };
+        if (total > 0) load_tiles(0);
         int32_t b = 0, s = 0, slot = 0;
         for (int64_t g = 0; g < total; ++g) {
             if (g >= kRing) wait_ge(L, kDecided, (int32_t)(g - kRing + 1), err);
-            const int32_t p = (b << 6) + lane;
-            const uint32_t t = (uint32_t)(t0 + s);
-            const U4 A = philox_stream(ch->seed, (uint32_t)p >> 3, t, kDomSweepHi, ch->rep, ch->inst);
-            const U4 B = philox_stream(ch->seed, (uint32_t)p >> 3, t, kDomSweepLo, ch->rep, ch->inst);
-            const uint32_t r = (half_word(A, (uint32_t)p & 7u) << 16) | half_word(B, (uint32_t)p & 7u);
+            uint32_t* tl = L.tile + ((size_t)slot * 64 + lane) * kTileWords;
+#pragma unroll
+            for (int d = 0; d < 2 * (kWin + 1); ++d) tl[d] = tw[d];
+            if (g + 1 < total) load_tiles(b + 1 == NB ? 0 : b + 1);
+            if ((g & 3) == 0) {
+                // one pass of the 64 lanes draws both streams' blocks of the
+                // next four spin blocks: lane 16 j + 8 h + q holds stream h
+                // (high / low half-words) of 8-position group q of block g + j
+                const int32_t j = lane >> 4;
+                int32_t bq = b + j, sq = s;
+                while (bq >= NB) {
+                    bq -= NB;
+                    ++sq;
+                }
+                const uint32_t dom = (lane >> 3) & 1 ? kDomSweepLo : kDomSweepHi;
+                const U4 A = philox_stream(ch->seed, (uint32_t)(bq * 8 + (lane & 7)), (uint32_t)(t0 + sq), dom,
+                                           ch->rep, ch->inst);
+                L.pr[lane] = make_uint4(A.x, A.y, A.z, A.w);
+                wave_sync_sk();
+            }
+            const uint32_t* pw = (const uint32_t*)(L.pr + (int)(g & 3) * 16 + (lane >> 3));
+            const uint32_t hsel = (uint32_t)lane & 7u;
+            const uint32_t r = (__builtin_amdgcn_ubfe(pw[hsel >> 1], 16u * (hsel & 1u), 16u) << 16) |
+                               __builtin_amdgcn_ubfe(pw[32 + (hsel >> 1)], 16u * (hsel & 1u), 16u);
             // starting guess from the logarithm, then exact fix-up on the table
             int32_t x0;
             const float slope = ch->xslope;
@@ -177,18 +224,6 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             while (x0 > 0 && !((unsigned long long)r < thr_at(L, ch, cached, x0))) --x0;
             while (x0 + 1 < ch->thr_len && (unsigned long long)r < thr_at(L, ch, cached, x0 + 1)) ++x0;
             L.xm[slot * 64 + lane] = x0;
-            // coupling tiles (bit-packed, bit 1 = J -1), columns of this block:
-            // row 64 b + lane, then rows 64 (b - d) + lane for d = 1..DW
-            const int32_t w0 = 2 * b, w1 = 2 * b + 1;
-            uint32_t* tl = L.tile + ((size_t)slot * 64 + lane) * kTileWords;
-#pragma unroll
-            for (int d = 0; d <= kWin; ++d) {
-                if (d > DW) break;
-                const int32_t bb = b - d < 0 ? b - d + NB : b - d;
-                const int32_t rr = (bb << 6) + lane;
-                tl[2 * d] = rr < n ? Jb[(int64_t)rr * wn + w0] : 0u;
-                tl[2 * d + 1] = (rr < n && w1 < wn) ? Jb[(int64_t)rr * wn + w1] : 0u;
-            }
             wave_release();
             if (lane == 0) st_rel(&L.sync[kPrepared], (int32_t)(g + 1));
             if (++slot == kRing) slot = 0;
@@ -292,16 +327,21 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                     for (int c = 0; c < 16; ++c) accb[c] = 0;
                     int32_t sum2 = 0;
                     for (int32_t f0 = 0; f0 < nf; f0 += 8) {
-                        // eight independent row loads in flight
+                        // eight independent row loads in flight: every load
+                        // is issued (entries past the last flip re-read the
+                        // last flip's row and are weighted 0), so no load
+                        // sits behind a branch that waits for the one before
                         uint32_t wv[8];
                         int32_t s2v[8];
 #pragma unroll
                         for (int i = 0; i < 8; ++i) {
                             const bool live = f0 + i < nf;
-                            const int32_t fv = live ? L.flips[slot * 64 + f0 + i] : 0;
+                            const int32_t fv = L.flips[slot * 64 + min(f0 + i, nf - 1)];
                             s2v[i] = live ? (fv < 0 ? -2 : 2) : 0;
-                            wv[i] = live ? Jb[(int64_t)((bk << 6) + (fv & 63)) * wn + wi] >> shift : 0u;
+                            wv[i] = Jb[(int64_t)((bk << 6) + (fv & 63)) * wn + wi];
                         }
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) wv[i] >>= shift;
 #pragma unroll
                         for (int i = 0; i < 8; ++i) {
                             sum2 += s2v[i];
@@ -485,7 +525,7 @@ size_t sk_lds_bytes(int32_t n)
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return r16((size_t)n * 4) + r16((wn + 2) * 4) + r16((size_t)kThrCache * 8) + r16(kRing * 64 * 4) +
            r16((size_t)kRing * 64 * kTileWords * 4) + r16(kRing * 64 * 4) + r16(kRing * 4) +
-           r16((4 + kRing) * 4);
+           r16((4 + kRing) * 4) + 64 * 16;
 }
 
 int sk_threads() { return kSkThreads; }
