@@ -156,7 +156,15 @@ typedef void (*sg_free_fn)(void* ptr, size_t bytes, void* user);
  *                   the graph stream); 0 = automatic.  Has no effect on any
  *                   result.
  *  threads_per_unit VB/SK: workgroup size (64..1024, multiple of 64); 0 =
- *                   automatic.  Has no effect on any result. */
+ *                   automatic.  Has no effect on any result.
+ *  split_members    VB: a large graph's unit can be spread over several
+ *                   workgroups that exchange each colour class's spins through
+ *                   HBM at a device-scope barrier.  0 = automatic (units far
+ *                   above one CU's share of the batch), 1 = never, k >= 2 =
+ *                   k workgroups for every unit with at least 2 k chunks of
+ *                   64 positions per wavefront in its largest colour class.
+ *                   Has no effect on any result; a barrier that times out
+ *                   (20 s) makes sg_measure return SG_EDEVICE. */
 typedef struct sg_opts {
     int64_t t_max;
     sg_alloc_fn alloc;
@@ -165,7 +173,7 @@ typedef struct sg_opts {
     int32_t chains_per_unit;
     int32_t threads_per_unit;
     uint32_t flags;
-    int32_t reserved;
+    int32_t split_members;
 } sg_opts;
 
 /* sg_opts.flags (VB contexts; no effect on any result) */

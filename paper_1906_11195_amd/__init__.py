@@ -54,7 +54,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("t_max", ctypes.c_int64), ("alloc", _ALLOC_FN), ("free", _FREE_FN),
                 ("user", ctypes.c_void_p), ("chains_per_unit", ctypes.c_int32),
                 ("threads_per_unit", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("split_members", ctypes.c_int32)]
 
 
 class _Obs(ctypes.Structure):
@@ -212,12 +212,13 @@ _ALLOC_CB = _ALLOC_FN(_torch_alloc)
 _FREE_CB = _FREE_FN(_torch_free)
 
 
-def _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags=0):
+def _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags=0, split_members=0):
     o = _Opts()
     o.t_max = int(t_max)
     o.chains_per_unit = int(chains_per_unit)
     o.threads_per_unit = int(threads_per_unit)
     o.flags = int(flags)
+    o.split_members = int(split_members)
     if torch_alloc:
         o.alloc, o.free = _ALLOC_CB, _FREE_CB
     return o
@@ -266,11 +267,11 @@ def _grid_len(t_max):
 
 def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
                  threads_per_unit: int = 0, torch_alloc: bool = True, autotune: bool = False,
-                 graph: bool = False) -> Context:
+                 graph: bool = False, split_members: int = 0) -> Context:
     keep = []
     arr = (_VbDesc * len(descs))(*[_vb_struct(d, keep) for d in descs])
     flags = (OPT_AUTOTUNE if autotune else 0) | (OPT_GRAPH if graph else 0)
-    o = _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags)
+    o = _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags, split_members)
     out = ctypes.c_void_p()
     _check(library().sg_create_vb(ctypes.byref(arr), len(descs), ctypes.byref(o), ctypes.byref(out)),
            "sg_create_vb")

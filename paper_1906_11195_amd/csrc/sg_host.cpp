@@ -340,6 +340,7 @@ struct sg_ctx {
         int threads = 64;
         size_t lds = 0;
         int32_t first = 0, count = 0;     // range in units_d
+        bool split = false;               // members of split units (not autotuned)
         int64_t updates = 0;              // chain-updates per sweep
         hipStream_t stream = nullptr;     // own stream for groups after the first
         hipEvent_t done = nullptr;
@@ -347,6 +348,8 @@ struct sg_ctx {
     std::vector<Group> groups;
     hipEvent_t fork = nullptr;
     int64_t* t_dev = nullptr;             // device counter of sweeps done
+    uint32_t* bars_d = nullptr;           // split units' barrier words, 2 per unit
+    int n_bar = 0;
     bool use_graph = false;
     hipStream_t capture_stream = nullptr; // for capturing when the caller uses the null stream
     std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;   // chunk length -> executable
@@ -465,7 +468,7 @@ void vb_launch_chunk(sg_ctx* c, int32_t nsw, hipStream_t s, const int64_t* t0p, 
         hip_check(hipEventRecord(c->groups[gi].done, c->groups[gi].stream));
         hip_check(hipStreamWaitEvent(s, c->groups[gi].done, 0));
     }
-    if (advance) hip_check(vb_advance(c->t_dev, nsw, s));
+    if (advance) hip_check(vb_advance(c->t_dev, nsw, c->bars_d, c->n_bar, s));
 }
 
 // The sweep chunk of length nsw captured once as a graph (kernels read the
@@ -538,6 +541,7 @@ void vb_autotune(sg_ctx* c)
     hip_check(hipEventCreate(&e0));
     hip_check(hipEventCreate(&e1));
     for (auto& G : c->groups) {
+        if (G.split) continue;   // members must meet at their barriers: keep the planned size
         int32_t nmax = 0;
         for (int32_t u = G.first; u < G.first + G.count; ++u) nmax = std::max(nmax, c->units[(size_t)u].n);
         const VbUnit& U0 = c->units[(size_t)G.first];
@@ -548,7 +552,7 @@ void vb_autotune(sg_ctx* c)
             size_t l = 0;
             for (int32_t u = G.first; u < G.first + G.count; ++u) {
                 const VbUnit& U = c->units[(size_t)u];
-                l = std::max(l, vb_lds_bytes(U.n, U.rpad, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
+                l = std::max(l, vb_lds_bytes(U.n, U.rpad, U.nch, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
             }
             return l;
         };
@@ -673,31 +677,21 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         int threads = 64;
         bool resident = false;
         int64_t work = 0;
+        int members = 1;
     };
+    // Workgroup size first: about three 64-position chunks per wavefront in
+    // the graph's largest colour class (up to 16 wavefronts).  Then as many
+    // chains per unit as fit in LDS at that size; only a graph whose single
+    // chain does not fit at that size gets fewer wavefronts.  (Spreading the
+    // chains of a large graph over several units keeps each unit's
+    // wavefronts busy; packing them at the cost of wavefronts leaves one
+    // latency-bound unit that finishes long after the rest.)
+    auto rpad_of = [](int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; };
+    std::vector<int> graph_threads(n_groups, 64);
     std::vector<UnitPlan> plan;
     for (size_t gi = 0; gi < n_groups; ++gi) {
-        const int64_t n = graphs[gi].n;
-        int32_t per = std::min<int32_t>(want, (int32_t)chains_of[gi].size());
-        auto rpad_of = [](int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; };
-        while (per > 1 && vb_lds_bytes((int32_t)n, rpad_of(per), 64) > lds_cap) --per;
-        if (vb_lds_bytes((int32_t)n, rpad_of(per), 64) > lds_cap) fail(SG_ENOTSUP);
-        const auto& ch = chains_of[gi];
-        for (size_t a = 0; a < ch.size(); a += (size_t)per) {
-            UnitPlan u;
-            u.group = (int32_t)gi;
-            u.chains.assign(ch.begin() + (long)a, ch.begin() + (long)std::min(ch.size(), a + (size_t)per));
-            u.rpad = rpad_of((int32_t)u.chains.size());
-            plan.push_back(std::move(u));
-        }
-    }
-
-    // workgroup size per unit: about three 64-position chunks per wavefront in
-    // its largest colour class, reduced until its LDS fits; small graphs keep
-    // their adjacency LDS-resident.  Units of one size form one launch group,
-    // largest work first inside a group (longest-processing-time order).
-    for (auto& u : plan) {
-        const VbGraph& g = graphs[(size_t)u.group];
-        const int32_t n = (int32_t)g.n;
+        const VbGraph& g = graphs[gi];
+        const int64_t n = g.n;
         int th = 64;
         if (o && o->threads_per_unit) {
             th = o->threads_per_unit;
@@ -708,29 +702,92 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
             int waves = 1;
             while (waves < 16 && waves * 3 < chunks) waves *= 2;
             th = 64 * waves;
-            while (th > 64 && vb_lds_bytes(n, u.rpad, th) > lds_cap) th /= 2;
+            while (th > 64 && vb_lds_bytes((int32_t)n, 1, 1, th) > lds_cap) th /= 2;
         }
-        if (vb_lds_bytes(n, u.rpad, th) > lds_cap) fail(SG_ENOTSUP);
+        graph_threads[gi] = th;
+        int32_t per = std::min<int32_t>(want, (int32_t)chains_of[gi].size());
+        while (per > 1 && vb_lds_bytes((int32_t)n, rpad_of(per), per, th) > lds_cap) --per;
+        if (vb_lds_bytes((int32_t)n, rpad_of(per), per, th) > lds_cap) fail(SG_ENOTSUP);
+        const auto& ch = chains_of[gi];
+        for (size_t a = 0; a < ch.size(); a += (size_t)per) {
+            UnitPlan u;
+            u.group = (int32_t)gi;
+            u.chains.assign(ch.begin() + (long)a, ch.begin() + (long)std::min(ch.size(), a + (size_t)per));
+            u.rpad = rpad_of((int32_t)u.chains.size());
+            plan.push_back(std::move(u));
+        }
+    }
+
+    // Small graphs keep their adjacency LDS-resident.  Units of one size form
+    // one launch group, largest work first inside a group
+    // (longest-processing-time order).
+    for (auto& u : plan) {
+        const VbGraph& g = graphs[(size_t)u.group];
+        const int32_t n = (int32_t)g.n;
+        const int th = graph_threads[(size_t)u.group];
+        if (vb_lds_bytes(n, u.rpad, (int32_t)u.chains.size(), th) > lds_cap) fail(SG_ENOTSUP);
         u.threads = th;
-        u.resident = vb_lds_bytes(n, u.rpad, th) + vb_resident_bytes(n, (int32_t)g.ent.size()) <= lds_cap;
+        u.resident = vb_lds_bytes(n, u.rpad, (int32_t)u.chains.size(), th) + vb_resident_bytes(n, (int32_t)g.ent.size()) <= lds_cap;
         u.work = (int64_t)n * (int64_t)u.chains.size();
     }
+    // Split units: a unit holding far more than one CU's share of the
+    // batch's work is spread over several workgroups (members) that meet at a
+    // device-scope barrier after every colour class.  Each member keeps at
+    // least two 64-position chunks per wavefront of the largest class, and
+    // the members of all split units of a context use at most a quarter of
+    // the CUs, so that they can all be resident at once next to other work.
+    // opts.split_members: 0 automatic, 1 never, k >= 2 every unit that has
+    // the chunks for k members (tests, tuning).  No effect on any result.
+    {
+        int n_cu = 0;
+        hip_check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+        const int forced = o ? o->split_members : 0;
+        int64_t total = 0;
+        for (const auto& u : plan) total += u.work;
+        const int64_t share = std::max<int64_t>(1, total / std::max(1, n_cu));
+        int budget = n_cu / 4;
+        std::vector<size_t> by_work(plan.size());
+        for (size_t i = 0; i < plan.size(); ++i) by_work[i] = i;
+        std::stable_sort(by_work.begin(), by_work.end(),
+                         [&](size_t a, size_t b) { return plan[a].work > plan[b].work; });
+        for (size_t i : by_work) {
+            UnitPlan& u = plan[i];
+            if (forced == 1 || u.resident) continue;
+            const VbGraph& g = graphs[(size_t)u.group];
+            int32_t maxcls = 0;
+            for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
+            const int64_t chunk_cap = ((maxcls + 63) / 64) / (2 * (u.threads / 64));
+            int64_t want = forced >= 2 ? forced : std::min<int64_t>(16, u.work / share);
+            want = std::min<int64_t>(want, std::min<int64_t>(chunk_cap, budget));
+            if (want >= 2) {
+                u.members = (int)want;
+                budget -= (int)want;
+            }
+        }
+    }
     std::stable_sort(plan.begin(), plan.end(), [](const UnitPlan& a, const UnitPlan& b) {
+        const bool sa = a.members > 1, sb = b.members > 1;
+        if (sa != sb) return sa;
         return a.threads != b.threads ? a.threads > b.threads : a.work > b.work;
     });
+    int n_split = 0, n_entries = 0;
+    for (const auto& u : plan) {
+        n_split += u.members > 1 ? 1 : 0;
+        n_entries += u.members;
+    }
 
     // device layout
     Arena A;
     std::vector<size_t> off_row(n_groups), off_ent(n_groups), off_cls(n_groups);
     for (size_t gi = 0; gi < n_groups; ++gi) {
         off_row[gi] = A.take(graphs[gi].row.size() * 4);
-        off_ent[gi] = A.take(std::max<size_t>(1, graphs[gi].ent.size()) * 4);
+        off_ent[gi] = A.take((graphs[gi].ent.size() + kVbEntPad) * 4);
         off_cls[gi] = A.take(graphs[gi].cls.size() * 4);
     }
     std::vector<size_t> off_state(plan.size());
     for (size_t u = 0; u < plan.size(); ++u) {
         const int64_t n = graphs[(size_t)plan[u].group].n;
-        off_state[u] = A.take((size_t)((n * plan[u].rpad + 31) / 32) * 4);
+        off_state[u] = A.take((size_t)VbLayout(plan[u].rpad).words(n) * 4);
     }
     std::vector<size_t> off_snap((size_t)c->n_chains), off_given((size_t)c->n_chains, 0);
     c->n_of.resize((size_t)count);
@@ -743,8 +800,10 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         }
         c->max_words = std::max(c->max_words, (int)wn);
     }
-    const size_t off_units = A.take(plan.size() * sizeof(VbUnit));
-    const size_t off_ids = A.take(plan.size() * kVbMaxChains * 4);
+    const size_t off_units = A.take((size_t)n_entries * sizeof(VbUnit));
+    const size_t off_ids = A.take((size_t)n_entries * kVbMaxChains * 4);
+    const size_t off_bars = A.take((size_t)std::max(1, n_split) * 8);
+    const size_t off_err = A.take(8);
     const size_t off_mc = A.take((size_t)c->n_chains * sizeof(MeasureChain));
     c->n_pairs = count * c->R * (c->R - 1) / 2;
     const size_t off_pairs = A.take((size_t)std::max(1, c->n_pairs) * 8);
@@ -761,8 +820,9 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     for (size_t gi = 0; gi < n_groups; ++gi) {
         const VbGraph& g = graphs[gi];
         hip_check(hipMemcpy(c->at<void>(off_row[gi]), g.row.data(), g.row.size() * 4, hipMemcpyHostToDevice));
-        if (!g.ent.empty())
-            hip_check(hipMemcpy(c->at<void>(off_ent[gi]), g.ent.data(), g.ent.size() * 4, hipMemcpyHostToDevice));
+        std::vector<uint32_t> padded(g.ent.size() + kVbEntPad, 0u);
+        std::copy(g.ent.begin(), g.ent.end(), padded.begin());
+        hip_check(hipMemcpy(c->at<void>(off_ent[gi]), padded.data(), padded.size() * 4, hipMemcpyHostToDevice));
         hip_check(hipMemcpy(c->at<void>(off_cls[gi]), g.cls.data(), g.cls.size() * 4, hipMemcpyHostToDevice));
     }
     for (int32_t i = 0; i < count; ++i) {
@@ -775,8 +835,13 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         }
     }
 
-    c->units.resize(plan.size());
-    std::vector<int32_t> ids(plan.size() * kVbMaxChains, 0);
+    c->units.clear();
+    c->units.reserve((size_t)n_entries);
+    std::vector<int32_t> ids((size_t)n_entries * kVbMaxChains, 0);
+    c->bars_d = c->at<uint32_t>(off_bars);
+    c->n_bar = 2 * n_split;
+    c->err_d = c->at<int>(off_err);
+    int split_seen = 0;
     c->chain_loc.resize((size_t)c->n_chains);
     c->updates_per_sweep = 0;
     for (size_t u = 0; u < plan.size(); ++u) {
@@ -796,9 +861,10 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         U.state = c->at<uint32_t>(off_state[u]);
         U.n = (int32_t)g.n;
         U.ncls = g.ncls;
+        if (g.ncls > 64) fail(SG_ENOTSUP);   // the kernel keeps <= 64 class bounds in LDS
         U.nch = (int32_t)plan[u].chains.size();
         U.rpad = plan[u].rpad;
-        U.state_words = (int32_t)((g.n * U.rpad + 31) / 32);
+        U.state_words = (int32_t)VbLayout(U.rpad).words(g.n);
         U.words_n = (int32_t)((g.n + 31) / 32);
         for (int32_t k = 0; k < U.nch; ++k) {
             const int32_t ch = plan[u].chains[(size_t)k];
@@ -815,21 +881,30 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
                 U.thr_hi[k][x] = (uint32_t)(th >> 16);
                 U.thr_lo[k][x] = (uint32_t)(th & 0xffffu);
             }
-            ids[u * kVbMaxChains + (size_t)k] = ch;
-            c->chain_loc[(size_t)ch] = {(int32_t)u, k};
+            c->chain_loc[(size_t)ch] = {(int32_t)c->units.size(), k};
         }
-        c->units[u] = U;
         const int th = plan[u].threads;
-        if (c->groups.empty() || c->groups.back().threads != th) {
+        const bool split = plan[u].members > 1;
+        U.members = plan[u].members;
+        U.err = c->err_d;
+        U.bar = split ? c->bars_d + 2 * split_seen++ : nullptr;
+        if (c->groups.empty() || c->groups.back().threads != th || c->groups.back().split != split) {
             sg_ctx::Group G;
             G.threads = th;
-            G.first = (int32_t)u;
+            G.split = split;
+            G.first = (int32_t)c->units.size();
             c->groups.push_back(G);
         }
         sg_ctx::Group& G = c->groups.back();
-        G.count++;
+        for (int m = 0; m < U.members; ++m) {
+            U.member = m;
+            for (int32_t k = 0; k < U.nch; ++k)
+                ids[c->units.size() * kVbMaxChains + (size_t)k] = plan[u].chains[(size_t)k];
+            c->units.push_back(U);
+            G.count++;
+        }
         G.updates += g.n * U.nch;
-        G.lds = std::max(G.lds, vb_lds_bytes(U.n, U.rpad, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
+        G.lds = std::max(G.lds, vb_lds_bytes(U.n, U.rpad, U.nch, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
         c->vb_threads = std::max(c->vb_threads, th);
         c->bond_lds = std::max(c->bond_lds, (size_t)(((U.nch * U.words_n + 1) & ~1) * 4 + kVbMaxChains * 8));
         c->updates_per_sweep += g.n * U.nch;
@@ -866,6 +941,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
     hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
     hip_check(zero_i64((long long*)c->t_dev, 2, nullptr));
+    hip_check(zero_i64((long long*)c->bars_d, (size_t)std::max(1, n_split), nullptr));
+    hip_check(zero_i64((long long*)c->err_d, 1, nullptr));
     hip_check(vb_init(c->units_d, (int)c->units.size(), 256, 0, nullptr));
     hip_check(vb_prepare());
     // every launch group after the first runs on a stream of its own, forked
@@ -1211,8 +1288,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
                 hip_check(hipMemcpyAsync(ovl.data(), c->overlap_d, (size_t)c->n_pairs * K * 8, hipMemcpyDeviceToHost, s));
             hip_check(hipMemcpyAsync(gram.data(), c->gram_d, gram.size() * 8, hipMemcpyDeviceToHost, s));
             hip_check(hipMemcpyAsync(acc.data(), c->acc_d, acc.size() * 8, hipMemcpyDeviceToHost, s));
-            if (c->kind == 1)
-                hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+            hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
             hip_check(hipStreamSynchronize(s));
             if (out->times)
                 for (int32_t k = 0; k < K; ++k) out->times[k] = c->times[(size_t)k];
@@ -1247,9 +1323,10 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
                     const int32_t i = ch / R, r = ch % R;
                     const auto& order = c->order_of_group[(size_t)c->group_of_inst[(size_t)i]];
                     int8_t* dst = out->spins + inst_base[(size_t)i] + (int64_t)r * U.n;
+                    const VbLayout lay(U.rpad);
                     for (int64_t p = 0; p < U.n; ++p) {
-                        const uint64_t b = (uint64_t)p * (uint64_t)U.rpad + (uint64_t)k;
-                        const uint32_t bit = (st[(size_t)u][(size_t)(b >> 5)] >> (b & 31u)) & 1u;
+                        const uint32_t bit =
+                            (st[(size_t)u][(size_t)lay.word(p, k)] >> lay.bit(p, k)) & 1u;
                         dst[order[(size_t)p]] = bit ? (int8_t)-1 : (int8_t)1;
                     }
                 }
@@ -1267,7 +1344,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
         }
     });
     if (st != SG_OK) return st;
-    if (err_flag & 2) return SG_EDEVICE;   // a sweep pipeline stalled and aborted
+    if (err_flag & 6) return SG_EDEVICE;   // a sweep pipeline stalled, or a split unit's barrier timed out
     return (err_flag & 1) ? SG_EPARITY : SG_OK;
 }
 

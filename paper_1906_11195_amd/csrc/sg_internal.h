@@ -19,17 +19,33 @@ __device__ __forceinline__ SG_G T* gl(T* p)
 }
 
 constexpr int kVbMaxChains = 8;    // chains per VB work unit
+constexpr int kVbEntPad = 8;       // zero entries after the adjacency (loads past a row stay in bounds)
 constexpr int kVbXMax = 64;        // threshold table length (max degree 63)
 constexpr int kMaxGrid = 32;       // grid times {0} U {2^k <= t_max}, t_max < 2^31
 constexpr int kSkTile = 64;        // SK decision block (one wavefront)
 constexpr int kSkThrLds = 1024;    // SK threshold entries cached in LDS
 
+// Packed spins of a VB work unit with `rpad` (1, 2, 4 or 8) chain slots,
+// "sliced" so that one 32-bit word holds P = 32 / rpad consecutive positions
+// of all rpad chains, chain c in bits [c P, c P + P) and position p at bit
+// c P + (p mod P): a word shifted right by (p mod P) has the bit of position p
+// of every chain at the bottom of that chain's field, so counting a bond for
+// all chains is a shift, an XOR and a mask.  Position p is in word p / P.
+// Bit value 1 = spin -1.
+struct VbLayout {
+    int32_t P;
+    __host__ __device__ explicit VbLayout(int32_t rpad) : P(32 / rpad) {}
+    __host__ __device__ int64_t words(int64_t n) const { return (n + P - 1) / P; }
+    __host__ __device__ int64_t word(int64_t p, int32_t) const { return p / P; }
+    __host__ __device__ int32_t bit(int64_t p, int32_t c) const { return c * P + (int32_t)(p % P); }
+};
+
 // One VB work unit = one workgroup: a graph in sweep (colour) order and up to
 // eight chains that share it.  The chains' spins live in LDS during a launch,
-// vertex-major: position p holds `rpad` bits, bit c belongs to chain c.
+// in the VbLayout packing (the same words as `state` between launches).
 struct VbUnit {
     const int32_t* row;        // [n+1] adjacency row starts, sweep order
-    const uint32_t* ent;       // [2m] neighbour position | (J < 0) << 31
+    const uint32_t* ent;       // [2m + kVbEntPad] neighbour position | (J < 0) << 31, then zeros
     const int32_t* cls;        // [ncls+1] first position of each colour class
     int32_t resident;          // 1: whole adjacency kept in LDS for the launch
     int32_t m2;                // 2m entries
@@ -46,10 +62,20 @@ struct VbUnit {
     int32_t ncls;
     int32_t nch;
     int32_t rpad;              // bits per position: 1, 2, 4 or 8 (>= nch)
-    int32_t state_words;       // ceil(n * rpad / 32)
+    int32_t state_words;       // VbLayout(rpad).words(n)
     int32_t words_n;           // ceil(n / 32)
     int32_t init_mode[kVbMaxChains];   // SG_START_* for the init kernel
     const uint32_t* given[kVbMaxChains];   // position-order bits when GIVEN
+    // A unit split over `members` workgroups (one descriptor each, member =
+    // 0 .. members - 1): every member keeps all spins in LDS, updates its
+    // share of each colour class's chunks, writes the spin words it changed
+    // through to `state`, meets the others at a device-scope barrier (bar[0]
+    // counts arrivals within the launch, bar[1] is an abort flag; both are
+    // zeroed before every launch) and reads the class's words back.
+    int32_t members;
+    int32_t member;
+    uint32_t* bar;
+    int* err;                  // bit 2 set when a barrier wait timed out
 };
 
 // One SK chain (a replica of an instance).
@@ -97,10 +123,11 @@ hipError_t vb_prepare();
 // n_sweeps to it on the stream (after every launch group of a chunk).
 hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_bytes, const int64_t* t0p,
                     int32_t n_sweeps, int64_t t_max, hipStream_t s);
-hipError_t vb_advance(int64_t* t, int32_t n_sweeps, hipStream_t s);
+// also zeroes the n_bar barrier words of split units for the next launch
+hipError_t vb_advance(int64_t* t, int32_t n_sweeps, uint32_t* bars, int n_bar, hipStream_t s);
 // LDS a unit needs for a launch with `threads` lanes per workgroup, and the
 // extra LDS that keeps its whole adjacency resident.
-size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads);
+size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads);
 size_t vb_resident_bytes(int32_t n, int32_t m2);
 
 // err_flag bit 0: recompute mismatch; bit 1: the sweep pipeline stalled.

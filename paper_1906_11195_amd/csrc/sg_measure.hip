@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(1024) vb_bond_kernel(const VbUnit* __restrict_
 {
     extern __shared__ uint32_t bsm[];
     const VbUnit* up = units + blockIdx.x;
+    if (up->member != 0) return;   // a split unit is measured once
     const int k = blockIdx.y;
     const int32_t n = up->n, wn = up->words_n, nch = up->nch;
     long long* red = (long long*)(bsm + ((nch * wn + 1) & ~1));

@@ -3,9 +3,13 @@
 // One workgroup owns one work unit: a graph stored in sweep order (the
 // colour classes of a proper colouring, the paper's bipartite parallel update
 // generalised; SI "Simulations of the Bethe Lattice on GPUs") and up to eight
-// chains that share it.  The chains' spins stay in LDS for the whole launch,
-// packed vertex-major (rpad bits per position, bit c = chain c), so that one
-// LDS read of a neighbour returns its spin in every chain.
+// chains that share it.  The chains' spins stay in LDS for the whole launch in
+// the sliced packing of VbLayout (one 32-bit word = P = 32 / rpad consecutive
+// positions of every chain, chain c in its own P-bit field), so that one LDS
+// read of a neighbour's word returns its spin in every chain and the
+// unsatisfied-bond counts of all chains advance with one shift, XOR, mask and
+// add (4-bit fields while every degree of the chunk is below 16, else two
+// sets of 8-bit fields).
 //
 // A sweep visits colour class 0, 1, ...; inside a class all positions are
 // independent (no two are adjacent).  A class is cut into aligned chunks of 64
@@ -19,10 +23,14 @@
 // Metropolis rule (Methods; SI bipartite-graph section): with x = s_p h_p the
 // move is accepted if x <= 0, else iff r < thr[x], thr[x] = floor(2^32
 // exp(-2x/T)).  r = (A << 16) | B with A, B half-words of two Philox streams.
-// The eight lanes of an aligned group of 8 positions share one Philox block
-// per chain: lane j computes the block of chain j and the group exchanges the
-// half-words through LDS.  B is computed only when A ties with the high half
-// of the threshold (probability 2^-16).
+// One Philox block serves the eight positions of an aligned group for one
+// chain.  A wavefront draws 64 blocks per pass (one per lane) into LDS: the
+// blocks of its next B = max(1, 8 / nch) chunks, so with 1, 2 or 4 chains no
+// lane draws a block nobody uses.  A is compared with the high half of the threshold,
+// read from a per-chain table indexed by 64 + x (entries for x <= 0 exceed
+// every A); B is computed only when A ties with it (probability 2^-16).  The
+// flips of a chunk are collected as one ballot per chain and written back by
+// one lane per spin word.
 #include "sg_internal.h"
 #include "sg_philox.h"
 
@@ -30,6 +38,8 @@ namespace sg {
 namespace {
 
 constexpr int kDMax = 8;   // adjacency entries prefetched per position
+constexpr int kTab = 128;  // threshold table per chain: index 64 + x, -63 <= x <= 63
+constexpr int kMaxCls = 64; // colour classes (greedy colouring, degree <= 63)
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -38,25 +48,60 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Compile-time form of VbLayout for a unit with RPAD chain slots.
+template <int RPAD>
+struct Sl {
+    static constexpr int P = 32 / RPAD;             // positions per word (= field width)
+    static constexpr int LP = RPAD == 1 ? 5 : RPAD == 2 ? 4 : RPAD == 4 ? 3 : 2;   // log2 P
+    // field bottoms; for RPAD 8 the 4-bit fields
+    static constexpr uint32_t M = RPAD == 1 ? 1u : RPAD == 2 ? 0x00010001u : RPAD == 4 ? 0x01010101u : 0x11111111u;
+    // byte offset in LDS of the word holding position (en & 0x7fffffff); the
+    // sign bit of an adjacency entry is masked off
+    static __device__ __forceinline__ uint32_t boff(uint32_t en)
+    {
+        return (en & (0x7fffffffu & ~(uint32_t)(P - 1))) >> (LP - 2);
+    }
+};
+
 struct VbLds {
-    uint32_t* sp;                 // spins, vertex-major
-    uint32_t* thi;                // [8][64]
-    uint32_t* tlo;                // [8][64]
+    uint32_t* sp;                 // spins, VbLayout words
+    uint32_t* thr;                // [8][kTab]: 64 + x -> thr[x] >> 16; 0x10000 for x <= 0
     unsigned long long* accs;     // [8]
-    uint4* xch;                   // [threads] Philox blocks
+    int32_t* flag;                // [4]: split units' abort flag
+    int32_t* cls;                 // [kMaxCls + 1] first position of each colour class
+    uint32_t* ri;                 // [8][2]: replica, instance of each chain
+    uint32_t* ctab;               // [waves][8][2]: first position and sweep of a batch's chunks
+    uint4* xch;                   // [waves][64] Philox blocks of a batch of chunks
     int32_t* area;                // resident adjacency: row starts, then entries
 };
 
-__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr)
+// Chunks whose Philox blocks one pass of 64 lanes draws.
+__host__ __device__ __forceinline__ int32_t vb_batch_chunks(int32_t nch)
+{
+    return nch <= 8 ? (8 / nch > 0 ? 8 / nch : 1) : 1;
+}
+
+__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr, int32_t nch)
 {
     VbLds L;
     L.sp = smem;
-    L.thi = smem + ((sw + 3) & ~3);
-    L.tlo = L.thi + kVbMaxChains * kVbXMax;
-    L.accs = (unsigned long long*)(L.tlo + kVbMaxChains * kVbXMax);
-    L.xch = (uint4*)(L.accs + kVbMaxChains);
-    L.area = (int32_t*)(L.xch + nthr);
+    L.thr = smem + ((sw + 3) & ~3);
+    L.accs = (unsigned long long*)(L.thr + kVbMaxChains * kTab);
+    L.flag = (int32_t*)(L.accs + kVbMaxChains);
+    L.cls = L.flag + 4;
+    L.ri = (uint32_t*)(L.cls + kMaxCls + 4);
+    L.ctab = L.ri + 2 * kVbMaxChains;
+    L.xch = (uint4*)(L.ctab + (nthr >> 6) * 2 * kVbMaxChains);
+    L.area = (int32_t*)(L.xch + (nthr >> 6) * 64);
     return L;
+}
+
+// Class bounds live in LDS and are read wave-uniformly: the cursor stays in
+// scalar registers and its reads never wait on the vector-memory counter that
+// the prefetched adjacency loads use.
+__device__ __forceinline__ int32_t cls_at(const int32_t* cls, int32_t k)
+{
+    return __builtin_amdgcn_readfirstlane(cls[k]);
 }
 
 // Chunk cursor of one wavefront: sweep s, colour class k, chunk j of the class
@@ -68,7 +113,7 @@ struct Cursor {
 template <class PC>
 __device__ __forceinline__ int32_t n_chunks(PC cls, int32_t k)
 {
-    const int32_t lo = cls[k], hi = cls[k + 1];
+    const int32_t lo = cls_at(cls, k), hi = cls_at(cls, k + 1);
     return hi > lo ? ((hi - 1) >> 6) - (lo >> 6) + 1 : 0;
 }
 
@@ -96,158 +141,322 @@ struct Stage {
 template <class PR, class PC>
 __device__ __forceinline__ void load_rows(PR row, PC cls, const Cursor& c, int lane, Stage& st)
 {
-    const int32_t lo = cls[c.k], hi = cls[c.k + 1];
+    const int32_t lo = cls_at(cls, c.k), hi = cls_at(cls, c.k + 1);
     st.q = (((lo >> 6) + c.j) << 6) + lane;
     const bool act = st.q >= lo && st.q < hi;
     st.r0 = act ? row[st.q] : 0;
     st.r1 = act ? row[st.q + 1] : 0;
 }
 
+// Loads kDMax entries from the row start whatever the degree (the adjacency
+// is followed by kVbEntPad zero entries): no load waits behind a branch.
 template <class PE>
 __device__ __forceinline__ void load_ents(PE ent, Stage& st)
 {
-    const int32_t deg = st.r1 - st.r0;
+    static_assert(kDMax <= kVbEntPad, "entry prefetch must stay inside the padded adjacency");
 #pragma unroll
-    for (int d = 0; d < kDMax; ++d) st.e[d] = d < deg ? ent[st.r0 + d] : 0u;
+    for (int d = 0; d < kDMax; ++d) st.e[d] = ent[st.r0 + d];
 }
 
-// Updates the positions of one chunk for every chain of the unit.
-template <int RPAD, class PE>
-__device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const VbLds& L, PE ent, const Stage& st,
-                                         int32_t lo, int32_t hi, uint32_t t, int32_t nch,
-                                         uint64_t key, uint32_t my_rep, uint32_t my_inst,
-                                         uint32_t* acc)
+// Metropolis decisions of one chunk for every chain, from the unsatisfied-bond
+// counts: chain c's count is the `width`-bit field of cA (c even or RPAD < 8)
+// or cB (c odd, RPAD 8) at bit fsh(c).  Returns, in lane j < 64 / P, spin
+// word j's flip mask; acc[c] += chain c's accepted flips.
+template <int RPAD>
+__device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, const VbLds& L, const uint32_t* gx,
+                                              uint32_t cA, uint32_t cB, bool wide, int32_t deg, bool act,
+                                              int32_t q, uint32_t t, int32_t nch, uint64_t key, uint32_t* acc)
 {
-    const int tid = threadIdx.x;
-    const int32_t q = st.q;
-    const int cc = tid & 7;
-
-    // Philox block of chain cc for the group of q (shared by the 8 lanes).
-    U4 A = U4{0, 0, 0, 0};
-    if (cc < nch) A = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepHi, my_rep, my_inst);
-    L.xch[tid] = make_uint4(A.x, A.y, A.z, A.w);
-    wave_sync();
-    if (q < lo || q >= hi) return;
-
-    const uint32_t ob = (uint32_t)q * RPAD;
-    const uint32_t own = L.sp[ob >> 5] >> (ob & 31u);
-    const int32_t deg = st.r1 - st.r0;
-    uint32_t c0 = 0, c1 = 0;
-    auto bond = [&](uint32_t en) {
-        const uint32_t qb = (en & 0x7fffffffu) * RPAD;
-        // bit c of f is 1 iff the bond (q, neighbour) is unsatisfied in chain c
-        const uint32_t f = (L.sp[qb >> 5] >> (qb & 31u)) ^ own ^ (uint32_t)((int32_t)en >> 31);
-        if (RPAD == 1) {
-            c0 += f & 1u;
-        } else {
-            // one byte counter per chain (degree <= 63)
-            c0 += ((f & 0xFu) * 0x00204081u) & 0x01010101u;
-            if (RPAD == 8) c1 += (((f >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
-        }
+    using S = Sl<RPAD>;
+    const int lane = threadIdx.x & 63;
+    const uint32_t hsel = (uint32_t)lane & 7u;
+    const uint32_t width = RPAD == 8 ? (wide ? 8u : 4u) : (uint32_t)S::P;
+    auto count = [&](int c) -> uint32_t {
+        if (RPAD == 1) return cA;
+        const uint32_t fsh = RPAD == 8 ? (wide ? 8u * (uint32_t)(c >> 1) : 4u * (uint32_t)c) : (uint32_t)(c * S::P);
+        return __builtin_amdgcn_ubfe(RPAD == 8 && (c & 1) ? cB : cA, fsh, width);
     };
-#pragma unroll
-    for (int d = 0; d < kDMax; ++d) {
-        if (!__any(d < deg)) break;
-        if (d < deg) bond(st.e[d]);
-    }
-    for (int32_t d = kDMax; d < deg; ++d) bond(ent[st.r0 + d]);
-
-    const uint32_t* gx = (const uint32_t*)(L.xch + (tid & ~7));
-    const uint32_t hsel = (uint32_t)tid & 7u;
-    uint32_t fl = 0;
+    // byte address of thr[c][64 + deg]; chain c's entry for its x = deg - 2 cnt
+    // is 8 cnt bytes below (plus c kTab words)
+    const int32_t tbase = (64 + deg) * 4;
+    const char* tb = (const char*)L.thr;
+    const uint32_t hs = 16u * (hsel & 1u);
+    // lane j < 64 / P assembles spin word j of the chunk from the ballots
+    const uint32_t sel = (uint32_t)(lane * S::P) >> 5;   // which half of a ballot
+    const uint32_t off = (uint32_t)(lane * S::P) & 31u;  // bit offset inside that half
+    auto fold = [&](int c, unsigned long long m) -> uint32_t {
+        const uint32_t h = sel ? (uint32_t)(m >> 32) : (uint32_t)m;
+        return (S::P == 32 ? h : (h >> off) & ((1u << (S::P & 31)) - 1u)) << (c * S::P);
+    };
+    uint32_t word = 0, tie = 0;
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) {
-        if (c >= nch) break;
-        const uint32_t cnt = RPAD == 1 ? c0 : (((c < 4) ? (c0 >> (8 * c)) : (c1 >> (8 * (c - 4)))) & 0xFFu);
-        const int32_t x = deg - 2 * (int32_t)cnt;   // x = s_q h_q
-        bool flip = x <= 0;
-        if (!flip) {
-            const uint32_t th = L.thi[c * kVbXMax + x];
-            const uint32_t rh = (gx[4 * c + (hsel >> 1)] >> (16u * (hsel & 1u))) & 0xffffu;
-            flip = rh < th;
-            if (rh == th) {
-                const U4 B = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
-                flip = half_word(B, hsel) < L.tlo[c * kVbXMax + x];
-            }
-        }
-        if (flip) {
-            fl |= 1u << c;
-            acc[c] += 1;
+        if (c < nch) {
+            const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + tbase - 8 * (int32_t)count(c));
+            const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
+            const unsigned long long m = __ballot(act && rh < th);
+            tie |= (act && rh == th) ? 1u << c : 0u;
+            acc[c] += (uint32_t)__popcll(m);
+            word |= fold(c, m);
         }
     }
-    if (fl) atomicXor(&L.sp[ob >> 5], fl << (ob & 31u));
+    if (__any(tie != 0u)) {
+        // A equals the high half of the threshold (those lanes did not flip
+        // above): decide on the low half
+#pragma unroll
+        for (int c = 0; c < RPAD; ++c) {
+            if (c < nch && __any((tie >> c) & 1u)) {
+                bool fl = false;
+                if ((tie >> c) & 1u) {
+                    const int32_t x = deg - 2 * (int32_t)count(c);
+                    const U4 Bk = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
+                    fl = half_word(Bk, hsel) < gl(&up->thr_lo[c][0])[x];
+                }
+                const unsigned long long m = __ballot(fl);
+                acc[c] += (uint32_t)__popcll(m);
+                word |= fold(c, m);
+            }
+        }
+    }
+    return word;
+}
+
+// Updates the positions of one chunk for every chain of the unit.  acc[c]
+// (wave-uniform) counts chain c's accepted flips since the last flush.
+// gx: this lane's group's Philox blocks of the chunk (chain c at gx + 4 c).
+template <int RPAD, bool SPLIT, class PE>
+__device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const VbLds& L, PE ent, const Stage& st,
+                                         int32_t lo, int32_t hi, uint32_t t, int32_t nch,
+                                         uint64_t key, const uint32_t* gx, uint32_t* acc)
+{
+    using S = Sl<RPAD>;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int32_t q = st.q;
+
+    const bool act = q >= lo && q < hi;
+    const int32_t deg = st.r1 - st.r0;   // 0 on inactive lanes
+    const char* spb = (const char*)L.sp;
+    const uint32_t qsh = (uint32_t)q & (uint32_t)(S::P - 1);
+    // own word, position q at the field bottoms
+    const uint32_t o0 = act ? *(const uint32_t*)(spb + S::boff((uint32_t)q)) >> qsh : 0u;
+    // bit c P of f: the bond to the neighbour is unsatisfied in chain c
+    auto unsat = [&](uint32_t en) {
+        const uint32_t sh = en & (uint32_t)(S::P - 1);
+        return (*(const uint32_t*)(spb + S::boff(en)) >> sh) ^ o0 ^ (uint32_t)((int32_t)en >> 31);
+    };
+    // per-chain counts of unsatisfied bonds: cA holds P-bit fields (for RPAD 8
+    // while every degree of the chunk is below 16), else for RPAD 8 cA / cB
+    // hold the even / odd chains in 8-bit fields
+    uint32_t cA = 0, cB = 0;
+    const bool wide = RPAD == 8 && __any(deg > 15);
+    if (!wide) {
+#pragma unroll
+        for (int d = 0; d < kDMax; ++d) {
+            if (!__any(d < deg)) break;
+            if (d < deg) cA += unsat(st.e[d]) & S::M;
+        }
+        for (int32_t d = kDMax; d < deg; ++d) cA += unsat(ent[st.r0 + d]) & S::M;
+    } else {
+        // rare (a degree above 15 in the chunk): entries re-read from the adjacency
+        for (int32_t d = 0; d < deg; ++d) {
+            const uint32_t f = unsat(ent[st.r0 + d]);
+            cA += f & 0x01010101u;
+            cB += (f >> 4) & 0x01010101u;
+        }
+    }
+
+    if (RPAD == 8 && !wide) cB = cA;
+    const uint32_t word = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key, acc);
+    // write the flips back: one lane per spin word of the chunk (a member of
+    // a split unit also writes the new word through to HBM)
+    if (lane < 64 / S::P && word) {
+        const uint32_t wi = ((uint32_t)(q - lane) >> S::LP) + (uint32_t)lane;
+        if (SPLIT) {
+            const uint32_t old = atomicXor(&L.sp[wi], word);
+            gl(up->state)[wi] = old ^ word;
+        } else {
+            atomicXor(&L.sp[wi], word);
+        }
+    }
+}
+
+// Split units: after a colour class, the members publish the words they
+// changed (already written through), meet at a device-scope barrier and read
+// the class's words back, so that every member's LDS copy is complete before
+// the next class.  The wait is bounded: a member that does not see all
+// arrivals within kBarrierTicks of the 100 MHz real-time clock raises the
+// unit's abort flag and the context's error bit, and every member stops.
+constexpr uint64_t kBarrierTicks = 2000000000ull;
+
+template <int RPAD>
+__device__ bool vb_exchange(const VbUnit* __restrict__ up, const VbLds& L, int32_t lo, int32_t hi,
+                            uint32_t target)
+{
+    using S = Sl<RPAD>;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t* bar = up->bar;
+        int32_t ab = 0;
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t start = wall_clock64();
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ab = 1;
+                break;
+            }
+            if (wall_clock64() - start > kBarrierTicks) {
+                __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicOr(up->err, 4);
+                ab = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        L.flag[0] = ab;
+    }
+    __syncthreads();
+    if (L.flag[0] != 0) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const SG_G uint32_t* gs = gl(up->state);
+    const int32_t w0 = lo >> S::LP, w1 = hi > lo ? ((hi - 1) >> S::LP) : w0 - 1;
+    for (int32_t w = w0 + (int32_t)threadIdx.x; w <= w1; w += (int32_t)blockDim.x) L.sp[w] = gs[w];
+    __syncthreads();
+    return true;
+}
+
+// Draws the Philox blocks of this wavefront's next chunks (up to B =
+// max(1, 8 / nch) of them, following cursor pc) into its LDS batch: block
+// m = i 8 nch + g nch + c is group g of chunk i for chain c (lanes past the
+// last such block draw nothing that is used).
+template <class PC>
+__device__ __forceinline__ void vb_fill(const VbLds& L, Cursor& pc, bool& pc_ok, PC cls, int32_t ncls,
+                                        int32_t nsw, int W, int wave, int wl, int lane, int64_t t0,
+                                        int32_t nch, uint64_t key)
+{
+    const int32_t B = vb_batch_chunks(nch);
+    uint32_t* ct = L.ctab + wl * 2 * kVbMaxChains;
+    for (int32_t i = 0; i < B; ++i) {
+        uint32_t base = 0u, tt = 0u;
+        if (pc_ok) {
+            base = (uint32_t)((((cls_at(cls, pc.k) >> 6) + pc.j) << 6));
+            tt = (uint32_t)(t0 + pc.s);
+            pc_ok = cursor_next(pc, W, wave, ncls, cls, nsw);
+        }
+        if (lane == 0) {
+            ct[2 * i] = base;
+            ct[2 * i + 1] = tt;
+        }
+    }
+    wave_sync();
+    const uint32_t mul = (65536u + (uint32_t)nch - 1u) / (uint32_t)nch;
+    {
+        const uint32_t m = (uint32_t)lane;
+        const uint32_t dq = (m * mul) >> 16;           // m / nch = 8 i + g
+        const uint32_t c = m - dq * (uint32_t)nch;
+        const uint32_t i = min(dq >> 3, (uint32_t)(B - 1)), g = dq & 7u;
+        const U4 A = philox_stream(key, (ct[2 * i] >> 3) + g, ct[2 * i + 1], kDomSweepHi, L.ri[2 * c],
+                                   L.ri[2 * c + 1]);
+        L.xch[wl * 64 + lane] = make_uint4(A.x, A.y, A.z, A.w);
+    }
+    wave_sync();
 }
 
 template <int RPAD>
 __device__ void vb_snapshot(const VbUnit* __restrict__ up, const uint32_t* __restrict__ sp, int k)
 {
-    const int32_t n = up->n, wn = up->words_n, nch = up->nch;
+    using S = Sl<RPAD>;
+    const int32_t wn = up->words_n, nch = up->nch, sw = up->state_words;
     for (int32_t idx = threadIdx.x; idx < nch * wn; idx += blockDim.x) {
         const int32_t c = idx / wn;
         const int32_t w = idx - c * wn;
         uint32_t bits = 0;
-        const int32_t pe = min(32, n - 32 * w);
-        for (int32_t i = 0; i < pe; ++i) {
-            const uint32_t b = (uint32_t)(32 * w + i) * RPAD + (uint32_t)c;
-            bits |= ((sp[b >> 5] >> (b & 31u)) & 1u) << i;
+#pragma unroll
+        for (int b = 0; b < 32 / S::P; ++b) {
+            const int32_t wi = w * (32 / S::P) + b;
+            const uint32_t v = wi < sw ? sp[wi] : 0u;
+            const uint32_t f = S::P == 32 ? v : (v >> (c * S::P)) & ((1u << (S::P & 31)) - 1u);
+            bits |= f << (b * S::P);
         }
         gl(up->snap[c])[(int64_t)k * wn + w] = bits;
     }
 }
 
-template <int RPAD, class PR, class PE, class PC>
-__device__ void vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
+template <int RPAD, bool SPLIT, class PR, class PE, class PC>
+__device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
                         int32_t nsw, int64_t t_max, int lane, int wave, int W);
 
-template <int RPAD, bool RES>
-__device__ void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0, int32_t nsw,
+// (each variant is a function of its own so that its registers are
+// allocated for it alone)
+template <int RPAD, bool RES, bool SPLIT>
+__device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0, int32_t nsw,
                        int64_t t_max)
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     // wave index made explicitly wave-uniform: the chunk cursor then lives in
-    // scalar registers and class bounds come from scalar loads
-    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), W = nthr >> 6;
+    // scalar registers and class bounds come from scalar loads; a member of a
+    // split unit numbers its wavefronts after those of the members before it
+    const int Wl = nthr >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) + (SPLIT ? up->member * Wl : 0));
+    const int W = SPLIT ? up->members * Wl : Wl;
     const int32_t sw = up->state_words, nch = up->nch, ncls = up->ncls;
-    const SG_G int32_t* __restrict__ cls = gl(up->cls);
-    const VbLds L = vb_carve(smem, sw, nthr);
+    const VbLds L = vb_carve(smem, sw, nthr, nch);
 
     const SG_G uint32_t* gstate = gl(up->state);
     for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = gstate[w];
-    for (int i = tid; i < kVbMaxChains * kVbXMax; i += nthr) {
-        L.thi[i] = (&up->thr_hi[0][0])[i];
-        L.tlo[i] = (&up->thr_lo[0][0])[i];
+    for (int i = tid; i < kVbMaxChains * kTab; i += nthr) {
+        const int c = i / kTab, x = i - c * kTab - 64;
+        L.thr[i] = x <= 0 ? 0x10000u : gl(&up->thr_hi[c][0])[x];
     }
-    if (tid < kVbMaxChains) L.accs[tid] = 0;
+    if (tid < kVbMaxChains) {
+        L.accs[tid] = 0;
+        L.ri[2 * tid] = up->rep[tid];
+        L.ri[2 * tid + 1] = up->inst[tid];
+    }
+    for (int32_t k = tid; k <= ncls; k += nthr) L.cls[k] = gl(up->cls)[k];
+    const int32_t* cls = L.cls;
+    __syncthreads();
     if (RES) {
         const int32_t n = up->n;
         const SG_G int32_t* grow = gl(up->row);
         const SG_G uint32_t* gent = gl(up->ent);
         for (int32_t i = tid; i <= n; i += nthr) L.area[i] = grow[i];
         uint32_t* re = (uint32_t*)(L.area + n + 1);
-        for (int32_t i = tid; i < up->m2; i += nthr) re[i] = gent[i];
+        for (int32_t i = tid; i < up->m2 + kVbEntPad; i += nthr) re[i] = i < up->m2 ? gent[i] : 0u;
         __syncthreads();
-        vb_loop<RPAD>(up, L, (const int32_t*)L.area, (const uint32_t*)(L.area + n + 1), cls, t0, nsw,
-                      t_max, lane, wave, W);
+        vb_loop<RPAD, false>(up, L, (const int32_t*)L.area, (const uint32_t*)(L.area + n + 1), cls, t0, nsw,
+                             t_max, lane, wave, W);
     } else {
-        vb_loop<RPAD>(up, L, gl(up->row), gl(up->ent), cls, t0, nsw, t_max, lane, wave, W);
+        vb_loop<RPAD, SPLIT>(up, L, gl(up->row), gl(up->ent), cls, t0, nsw, t_max, lane, wave, W);
     }
-    for (int32_t w = tid; w < sw; w += nthr) gl(up->state)[w] = L.sp[w];
+    // (split units keep `state` current by writing through)
+    if (!SPLIT)
+        for (int32_t w = tid; w < sw; w += nthr) gl(up->state)[w] = L.sp[w];
     __syncthreads();
     if (tid < nch) atomicAdd(up->accepted[tid], L.accs[tid]);
 }
 
-// The sweep loop of one unit, for adjacency pointers in HBM or in LDS.
-template <int RPAD, class PR, class PE, class PC>
-__device__ void vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
+// The sweep loop of one unit (or of one member of a split unit: `wave` and
+// `W` then count the wavefronts of all members), for adjacency pointers in
+// HBM or in LDS.  False if a split unit's barrier aborted.
+template <int RPAD, bool SPLIT, class PR, class PE, class PC>
+__device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
                         int32_t nsw, int64_t t_max, int lane, int wave, int W)
 {
     const int tid = threadIdx.x;
     const int32_t nch = up->nch, ncls = up->ncls;
-    // chain whose Philox block this lane computes
     const uint64_t key = up->key;
-    const int cc = tid & 7;
-    const uint32_t my_rep = cc < nch ? up->rep[cc] : 0u;
-    const uint32_t my_inst = cc < nch ? up->inst[cc] : 0u;
+    const int wl = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront inside the workgroup
+    // Philox batches: cursor of the next chunk to draw for, chunks left in
+    // the current batch and the batch position of the next chunk
+    const int32_t B = vb_batch_chunks(nch);
+    Cursor pc{0, 0, wave - W};
+    bool pc_ok = nsw > 0 && cursor_next(pc, W, wave, ncls, cls, nsw);
+    int32_t left = 0, bi = 0;
+    const uint32_t* xg = (const uint32_t*)(L.xch + wl * 64);
+    const uint32_t lane_off = (uint32_t)(lane >> 3) * (uint32_t)nch * 4u + (((uint32_t)lane & 7u) >> 1);
 
     // pipeline: E = chunk to update next (rows + entries), R = the one after
     // (rows only)
@@ -262,14 +471,14 @@ __device__ void vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
     }
     __syncthreads();
 
-    uint32_t acc[RPAD];
+    uint32_t acc[RPAD];   // wave-uniform; flushed to LDS once per sweep
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) acc[c] = 0;
 
     for (int32_t s = 0; s < nsw; ++s) {
         const uint32_t t = (uint32_t)(t0 + s);
         for (int32_t k = 0; k < ncls; ++k) {
-            const int32_t lo = cls[k], hi = cls[k + 1];
+            const int32_t lo = cls_at(cls, k), hi = cls_at(cls, k + 1);
             const int32_t nck = n_chunks(cls, k);
             for (int32_t j = wave; j < nck; j += W) {
                 const Stage cur = E;
@@ -281,19 +490,37 @@ __device__ void vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
                     haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
                     if (haveR) load_rows(row, cls, cR, lane, R);
                 }
-                vb_chunk<RPAD>(up, L, ent, cur, lo, hi, t, nch, key, my_rep, my_inst, acc);
+                if (left == 0) {
+                    vb_fill(L, pc, pc_ok, cls, ncls, nsw, W, wave, wl, lane, t0, nch, key);
+                    left = B;
+                    bi = 0;
+                }
+                vb_chunk<RPAD, SPLIT>(up, L, ent, cur, lo, hi, t, nch, key,
+                                      xg + (uint32_t)bi * 32u * (uint32_t)nch + lane_off, acc);
+                --left;
+                ++bi;
             }
-            __syncthreads();
+            if (SPLIT) {
+                if (!vb_exchange<RPAD>(up, L, lo, hi, (uint32_t)up->members * (uint32_t)(s * ncls + k + 1)))
+                    return false;
+            } else {
+                __syncthreads();
+            }
         }
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < RPAD; ++c)
+                if (c < nch && acc[c]) atomicAdd(&L.accs[c], (unsigned long long)acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < RPAD; ++c) acc[c] = 0;
         const int64_t tn = t0 + s + 1;
         if (tn <= t_max && (tn & (tn - 1)) == 0) {
-            vb_snapshot<RPAD>(up, L.sp, 1 + (63 - __clzll((unsigned long long)tn)));
+            if (!SPLIT || up->member == 0) vb_snapshot<RPAD>(up, L.sp, 1 + (63 - __clzll((unsigned long long)tn)));
             __syncthreads();
         }
     }
-#pragma unroll
-    for (int c = 0; c < RPAD; ++c)
-        if (c < nch && acc[c]) atomicAdd(&L.accs[c], (unsigned long long)acc[c]);
+    return true;
 }
 
 // t0p: device-resident number of sweeps done before this launch (read once;
@@ -308,30 +535,39 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
     const int64_t t0 = *gl(t0p);
     if (up->resident) {
         switch (up->rpad) {
-            case 1: vb_run<1, true>(up, smem, t0, nsw, t_max); break;
-            case 2: vb_run<2, true>(up, smem, t0, nsw, t_max); break;
-            case 4: vb_run<4, true>(up, smem, t0, nsw, t_max); break;
-            default: vb_run<8, true>(up, smem, t0, nsw, t_max); break;
+            case 1: vb_run<1, true, false>(up, smem, t0, nsw, t_max); break;
+            case 2: vb_run<2, true, false>(up, smem, t0, nsw, t_max); break;
+            case 4: vb_run<4, true, false>(up, smem, t0, nsw, t_max); break;
+            default: vb_run<8, true, false>(up, smem, t0, nsw, t_max); break;
+        }
+    } else if (up->members > 1) {
+        switch (up->rpad) {
+            case 1: vb_run<1, false, true>(up, smem, t0, nsw, t_max); break;
+            case 2: vb_run<2, false, true>(up, smem, t0, nsw, t_max); break;
+            case 4: vb_run<4, false, true>(up, smem, t0, nsw, t_max); break;
+            default: vb_run<8, false, true>(up, smem, t0, nsw, t_max); break;
         }
     } else {
         switch (up->rpad) {
-            case 1: vb_run<1, false>(up, smem, t0, nsw, t_max); break;
-            case 2: vb_run<2, false>(up, smem, t0, nsw, t_max); break;
-            case 4: vb_run<4, false>(up, smem, t0, nsw, t_max); break;
-            default: vb_run<8, false>(up, smem, t0, nsw, t_max); break;
+            case 1: vb_run<1, false, false>(up, smem, t0, nsw, t_max); break;
+            case 2: vb_run<2, false, false>(up, smem, t0, nsw, t_max); break;
+            case 4: vb_run<4, false, false>(up, smem, t0, nsw, t_max); break;
+            default: vb_run<8, false, false>(up, smem, t0, nsw, t_max); break;
         }
     }
 }
 
-__global__ void vb_advance_kernel(int64_t* t, int32_t nsw)
+__global__ void vb_advance_kernel(int64_t* t, int32_t nsw, uint32_t* bars, int n_bar)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *t += nsw;
+    for (int i = threadIdx.x; i < n_bar; i += blockDim.x) bars[i] = 0u;
 }
 
 // Initial configurations and the t = 0 snapshot.
 __global__ void __launch_bounds__(1024) vb_init_kernel(const VbUnit* __restrict__ units)
 {
     const VbUnit* up = units + blockIdx.x;
+    if (up->member != 0) return;   // members of a split unit share its state
     const int32_t n = up->n, wn = up->words_n, nch = up->nch, rpad = up->rpad;
     for (int32_t idx = threadIdx.x; idx < nch * wn; idx += blockDim.x) {
         const int32_t c = idx / wn;
@@ -351,16 +587,14 @@ __global__ void __launch_bounds__(1024) vb_init_kernel(const VbUnit* __restrict_
         up->snap[c][w] = bits;
     }
     __syncthreads();
-    const int32_t per = 32 / rpad;
+    const VbLayout lay(rpad);
     for (int32_t w = threadIdx.x; w < up->state_words; w += blockDim.x) {
+        const int32_t p0 = w * lay.P;   // first position of the word
         uint32_t word = 0;
-        for (int32_t i = 0; i < per; ++i) {
-            const int32_t p = w * per + i;
-            if (p >= n) break;
-            for (int32_t c = 0; c < nch; ++c) {
-                const uint32_t b = (up->snap[c][p >> 5] >> (p & 31)) & 1u;
-                word |= b << (i * rpad + c);
-            }
+        for (int32_t c = 0; c < nch; ++c) {
+            const uint32_t v = up->snap[c][p0 >> 5];
+            const uint32_t f = lay.P == 32 ? v : (v >> (p0 & 31)) & ((1u << lay.P) - 1u);
+            word |= f << (c * lay.P);
         }
         up->state[w] = word;
     }
@@ -370,14 +604,15 @@ __global__ void __launch_bounds__(1024) vb_init_kernel(const VbUnit* __restrict_
 
 size_t vb_resident_bytes(int32_t n, int32_t m2)
 {
-    return ((size_t)(n + 1 + m2) * 4 + 15) & ~(size_t)15;
+    return ((size_t)(n + 1 + m2 + kVbEntPad) * 4 + 15) & ~(size_t)15;
 }
 
-size_t vb_lds_bytes(int32_t n, int32_t rpad, int threads)
+size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads)
 {
-    const size_t sw = ((size_t)n * (size_t)rpad + 31) / 32;
-    return ((sw + 3) & ~(size_t)3) * 4 + 2 * kVbMaxChains * kVbXMax * 4 + kVbMaxChains * 8 +
-           (size_t)threads * 16;
+    const size_t sw = (size_t)VbLayout(rpad).words(n);
+    const size_t waves = (size_t)threads / 64;
+    return ((sw + 3) & ~(size_t)3) * 4 + (size_t)kVbMaxChains * kTab * 4 + kVbMaxChains * 8 + 16 +
+           (kMaxCls + 4) * 4 + kVbMaxChains * 8 + waves * kVbMaxChains * 8 + waves * 64 * 16;
 }
 
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStream_t s)
@@ -408,9 +643,9 @@ hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_by
     return hipGetLastError();
 }
 
-hipError_t vb_advance(int64_t* t, int32_t n_sweeps, hipStream_t s)
+hipError_t vb_advance(int64_t* t, int32_t n_sweeps, uint32_t* bars, int n_bar, hipStream_t s)
 {
-    hipLaunchKernelGGL(vb_advance_kernel, dim3(1), dim3(64), 0, s, t, n_sweeps);
+    hipLaunchKernelGGL(vb_advance_kernel, dim3(1), dim3(256), 0, s, t, n_sweeps, bars, n_bar);
     return hipGetLastError();
 }
 
