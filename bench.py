@@ -280,7 +280,9 @@ def main():
     ap.add_argument("--sk-sweeps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only-vb", action="store_true")
+    ap.add_argument("--only-vb", action="store_true", help="the batched VB leg only (same as --legs vb)")
+    ap.add_argument("--legs", default="vb,plain,sk,uneven,serving",
+                    help="comma-separated legs to run besides the headline: plain, sk, uneven, serving")
     ap.add_argument("--uneven-sweeps", type=int, default=128)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -316,13 +318,17 @@ def main():
     vb = run_vb_batched(args, torch, sg, workloads)
     log("VB batched: %.1f updates/ns" % vb["value"])
     plain = sk = uneven = serve = None
-    if not args.only_vb:
+    legs = set() if args.only_vb else set(x.strip() for x in args.legs.split(","))
+    if "plain" in legs:
         plain = run_vb_plain(args, torch, sg, workloads)
         log("VB plain: p50 %.2f ms" % plain["p50_ms"])
+    if "sk" in legs:
         sk = run_sk(args, torch, sg, workloads)
         log("SK: %.2f updates/ns" % sk["updates_per_ns"])
+    if "uneven" in legs:
         uneven = run_uneven(args, torch, sg, workloads)
         log("VB uneven: %.1f updates/ns" % uneven["updates_per_ns"])
+    if "serving" in legs:
         serve = run_serving(args, torch, sg, workloads)
         log("serving: p50 %.1f ms, p99 %.1f ms" % (serve.get("p50_ms", 0), serve.get("p99_ms", 0)))
     cpu = None

@@ -82,81 +82,139 @@ def run_alone(req, flags: int = MEASURE_OBS | MEASURE_SPINS) -> dict:
         sg_free(ctx)
 
 
+def select_batch(pending, now: float, time_scale: float, used: int, active_requests: int, budget: int,
+                 max_batch: int, max_active: int):
+    """The next batch: requests that have arrived by `now` with the same
+    (kind, sweeps) as the oldest arrived one, in arrival order, as long as the
+    batch stays within max_batch, the slot limit and the HBM budget (a batch
+    always gets its first request when nothing else is running).  Returns
+    (batch, its footprint in bytes)."""
+    arrived = [r for r in pending if r.arrival * time_scale <= now]
+    if not arrived:
+        return [], 0
+    key = (arrived[0].kind, arrived[0].sweeps)
+    batch, fp_sum = [], 0
+    for r in arrived:
+        if (r.kind, r.sweeps) != key:
+            continue
+        if len(batch) >= max_batch or active_requests + len(batch) >= max_active:
+            break
+        fp = footprint_bytes(r.kind, r.n, r.sweeps)
+        if used + fp_sum + fp > budget and (batch or active_requests):
+            break
+        batch.append(r)
+        fp_sum += fp
+    return batch, fp_sum
+
+
 class AgingServer:
+    """Continuous-batching loop over a pool of streams.
+
+    A free stream takes every request that has arrived with the same kind and
+    run length as the oldest waiting one (up to `max_batch`, within the HBM
+    budget) and runs them as one context: all their chains advance in the same
+    launches (large VB graphs split over several workgroups), and new
+    arrivals form the next batch on the next free stream while earlier ones
+    run.  A batch is measured and released when its runs are done; each
+    request's result is its own slice of the batch's observables, identical to
+    the run alone."""
+
     def __init__(self, hbm_budget: int = 32 << 30, max_active: int = 64, chunk_sweeps: int = 256,
-                 n_streams: int = 4, flags: int = MEASURE_OBS | MEASURE_SPINS):
+                 n_streams: int = 4, flags: int = MEASURE_OBS | MEASURE_SPINS, max_batch: int = 64):
         import torch
         self.torch = torch
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
+        self.max_batch = int(max_batch)
         self.chunk = int(chunk_sweeps)
         self.flags = flags
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
 
+    def _take_batch(self, pending, now, time_scale, used, active_requests):
+        return select_batch(pending, now, time_scale, used, active_requests, self.budget, self.max_batch,
+                            self.max_active)
+
     def run(self, requests, time_scale: float = 1.0, max_wall: Optional[float] = None) -> List[Result]:
-        """Serves `requests` (sorted by arrival time, seconds from the start,
-        scaled by time_scale).  Returns one Result per finished request."""
+        """Serves `requests` (arrival times in seconds from the start, scaled by
+        time_scale).  Returns one Result per finished request."""
         torch = self.torch
         pending = sorted(requests, key=lambda r: r.arrival)
-        active: Dict[int, dict] = {}
+        free = list(range(len(self.streams)))
+        batches = []
         used = 0
         results: List[Result] = []
         t0 = time.perf_counter()
-        next_stream = 0
-        while pending or active:
+        while pending or batches:
             now = time.perf_counter() - t0
             if max_wall is not None and now > max_wall:
                 break
-            # admission: arrived requests, free slot, footprint within budget
-            while pending and pending[0].arrival * time_scale <= now and len(active) < self.max_active:
-                req = pending[0]
-                fp = footprint_bytes(req.kind, req.n, req.sweeps)
-                if used + fp > self.budget and active:
-                    break
-                pending.pop(0)
-                stream = self.streams[next_stream % len(self.streams)]
-                next_stream += 1
-                with torch.cuda.stream(stream):
-                    d = descriptor(req)
-                    ctx = (sg_create_vb if req.kind == "vb" else sg_create_sk)([d], t_max=req.sweeps)
-                active[req.rid] = dict(req=req, ctx=ctx, stream=stream, done=0, event=None, fp=fp,
-                                       admitted=time.perf_counter() - t0)
-                used += fp
             progressed = False
-            for rid in list(active):
-                a = active[rid]
-                ev = a["event"]
+            # admission: a free stream takes the next batch
+            while free and pending:
+                n_active = sum(len(b["reqs"]) for b in batches)
+                batch, fp = self._take_batch(pending, now, time_scale, used, n_active)
+                if not batch:
+                    break
+                ids = set(id(r) for r in batch)
+                pending = [r for r in pending if id(r) not in ids]
+                si = free.pop(0)
+                stream = self.streams[si]
+                with torch.cuda.stream(stream):
+                    descs = [descriptor(r) for r in batch]
+                    make = sg_create_vb if batch[0].kind == "vb" else sg_create_sk
+                    ctx = make(descs, t_max=batch[0].sweeps)
+                batches.append(dict(reqs=batch, ctx=ctx, si=si, stream=stream, done=0, event=None, fp=fp,
+                                    admitted=time.perf_counter() - t0))
+                used += fp
+                progressed = True
+            for b in list(batches):
+                ev = b["event"]
                 if ev is not None and not ev.query():
                     continue
-                req = a["req"]
-                if a["done"] >= req.sweeps:
-                    obs = sg_measure(a["ctx"], self.flags, stream=a["stream"])
-                    sg_free(a["ctx"])
+                length = b["reqs"][0].sweeps
+                if b["done"] >= length:
+                    obs = sg_measure(b["ctx"], self.flags, stream=b["stream"])
+                    sg_free(b["ctx"])
                     fin = time.perf_counter() - t0
-                    results.append(Result(rid, req.kind, req.n, req.sweeps, req.arrival * time_scale,
-                                          a["admitted"], fin, obs))
-                    used -= a["fp"]
-                    del active[rid]
+                    for i, req in enumerate(b["reqs"]):
+                        results.append(Result(req.rid, req.kind, req.n, req.sweeps, req.arrival * time_scale,
+                                              b["admitted"], fin, _slice(obs, i)))
+                    used -= b["fp"]
+                    free.append(b["si"])
+                    batches.remove(b)
                     progressed = True
                     continue
-                k = min(self.chunk, req.sweeps - a["done"])
-                sg_sweep(a["ctx"], k, stream=a["stream"])
-                a["done"] += k
+                k = min(self.chunk, length - b["done"])
+                sg_sweep(b["ctx"], k, stream=b["stream"])
+                b["done"] += k
                 ev = torch.cuda.Event()
-                ev.record(a["stream"])
-                a["event"] = ev
+                ev.record(b["stream"])
+                b["event"] = ev
                 progressed = True
             if not progressed:
-                if active:
+                if batches:
                     time.sleep(0.0002)
                 elif pending:
                     wait = pending[0].arrival * time_scale - (time.perf_counter() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
-        for a in active.values():
+        for b in batches:
             torch.cuda.synchronize()
-            sg_free(a["ctx"])
+            sg_free(b["ctx"])
         return results
+
+
+def _slice(obs: dict, i: int) -> dict:
+    """Instance i's observables, shaped like a one-instance context's."""
+    out = {}
+    for key, v in obs.items():
+        if key in ("bond", "overlap", "gram", "accepted") and isinstance(v, np.ndarray):
+            out[key] = v[i:i + 1]
+        elif key == "spins" and v is not None:
+            out[key] = [v[i]]
+        else:
+            out[key] = v
+    return out
 
 
 def latency_stats(results: List[Result]) -> dict:
