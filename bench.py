@@ -156,19 +156,26 @@ def run_vb_batched(args, torch, sg, workloads):
 def run_vb_plain(args, torch, sg, workloads):
     """Plain one-instance run (1024 spins, 2 replicas, 4096 sweeps): run latency."""
     d = workloads.vb_plain()
-    lat = []
+    lat, parts = [], []
     for rep in range(args.plain_runs):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = sg.sg_create_vb(d, t_max=workloads.VB_PLAIN_SWEEPS)
+        t1 = time.perf_counter()
         sg.sg_sweep(ctx, workloads.VB_PLAIN_SWEEPS)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         sg.sg_measure(ctx, sg.MEASURE_OBS)
         sg.sg_free(ctx)
-        lat.append(time.perf_counter() - t0)
+        t3 = time.perf_counter()
+        lat.append(t3 - t0)
+        parts.append((t1 - t0, t2 - t1, t3 - t2))
     upd = 1024 * 2 * workloads.VB_PLAIN_SWEEPS
+    med = [percentile([p[i] for p in parts], 50) * 1e3 for i in range(3)]
     return dict(workload="VB plain: N=1024, 2 replicas, T=0.8, 4096 sweeps (create + sweeps + measure)",
                 updates_per_ns=upd / (percentile(lat, 50) * 1e9),
-                p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3, runs=len(lat))
+                p50_ms=percentile(lat, 50) * 1e3, p99_ms=percentile(lat, 99) * 1e3, runs=len(lat),
+                create_ms=round(med[0], 3), sweeps_ms=round(med[1], 3), measure_ms=round(med[2], 3))
 
 
 def run_sk(args, torch, sg, workloads):

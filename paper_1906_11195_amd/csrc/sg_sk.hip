@@ -21,7 +21,7 @@
 //    result is the plain sequential sweep.  The block's flips are published to
 //    a ring buffer.
 //  * updater wavefronts: apply each published block's flips to all other fields
-//    (H_k += 2 s_j J_jk, rows read bit-packed, 16 fields per lane), lagging one
+//    (H_k += 2 s_j J_jk, rows read bit-packed, a few fields per lane), lagging one
 //    block behind; they skip the flipped block (patched in the decider) and the
 //    next block (corrected by the decider from its tile), except for the last
 //    block of a launch.
@@ -51,9 +51,14 @@ constexpr int kWin = SG_SK_WIN;     // previous blocks the decider corrects for 
 constexpr int kTileWords = 2 + 2 * kWin;   // per lane: own-block row, kWin previous rows
 constexpr int kThrCache = 512;      // threshold entries cached in LDS
 #ifndef SG_SK_UPD
-#define SG_SK_UPD 4
+#define SG_SK_UPD 8
+#endif
+#ifndef SG_SK_COLS
+#define SG_SK_COLS 8
 #endif
 constexpr int kUpdWaves = SG_SK_UPD;   // updater wavefronts
+constexpr int kUpdCols = SG_SK_COLS;   // fields one updater lane owns (4, 8 or 16)
+static_assert(kUpdCols == 4 || kUpdCols == 8 || kUpdCols == 16, "updater item width");
 constexpr int kSkThreads = 64 * (2 + kUpdWaves);
 constexpr int kSpinLimit = 1 << 22; // bounded waits: a stuck pipeline aborts
 static_assert(kRing >= kWin + 1, "flip batches must outlive the correction window");
@@ -234,6 +239,9 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         }
     } else if (wave == 0) {
         // ---------------- decider ----------------
+        // the sequential critical path: issue ahead of the wavefronts that
+        // share its SIMD
+        __builtin_amdgcn_s_setprio(3);
         uint32_t acc = 0;
         int32_t b = 0, s = 0, slot = 0;
         for (int64_t g = 0; g < total; ++g) {
@@ -255,8 +263,10 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                 int ps = slot - d;
                 if (ps < 0) ps += kRing;
                 const int32_t nfp = L.nflip[ps];
+                // the block's flips in one LDS read (lane f holds flip f)
+                const int32_t fvl = L.flips[ps * 64 + lane];
                 for (int32_t f = 0; f < nfp; ++f) {
-                    const int32_t fv = __builtin_amdgcn_readfirstlane(L.flips[ps * 64 + f]);
+                    const int32_t fv = __builtin_amdgcn_readlane(fvl, f);
                     const int jf = fv & 63;
                     const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)e0, jf)
                                                  : (uint32_t)__builtin_amdgcn_readlane((int)e1, jf);
@@ -264,7 +274,7 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                     Hp += (fv < 0 ? -2 : 2) * jv;
                 }
             }
-            int32_t start = 0, nf = 0;
+            int32_t start = 0, nf = 0, myflip = 0;   // lane f records flip f
             for (;;) {
                 const int32_t x = sb ? -Hp : Hp;
                 const bool flip = act && lane >= start && x <= xm;
@@ -277,11 +287,12 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                                              : (uint32_t)__builtin_amdgcn_readlane((int)d1, j);
                 const int32_t jv = ((w >> sh) & 1u) ? -1 : 1;
                 if (lane != j) Hp += (nb ? -2 : 2) * jv;
-                if (lane == 0) L.flips[slot * 64 + nf] = j | (int32_t)(nb << 31);
+                if (lane == nf) myflip = j | (int32_t)(nb << 31);
                 ++nf;
                 start = j + 1;
             }
             if (act) L.H[p] = Hp;
+            if (lane < nf) L.flips[slot * 64 + lane] = myflip;
             const unsigned long long mask = __ballot(sb != 0u);
             if (lane == 0) {
                 L.bits[2 * b] = (uint32_t)mask;
@@ -305,8 +316,10 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         if (lane == 0 && acc) atomicAdd(ch->accepted, (unsigned long long)acc);
     } else {
         // ---------------- updaters ----------------
+        // updater lane items: kUpdCols consecutive fields (one slice of a
+        // coupling-row word)
         const int ut = tid - 128;
-        const int32_t nhalf = (n + 15) >> 4;
+        const int32_t nitem = (n + kUpdCols - 1) / kUpdCols;
         int32_t bk = 0, slot = 0;
         for (int64_t k = 0; k < total; ++k) {
             wait_ge(L, kDecided, (int32_t)(k + 1), err);
@@ -315,16 +328,16 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             // this batch from the decider's correction
             const int32_t dskip = (int32_t)min((int64_t)DW, total - 1 - k);
             if (nf > 0) {
-                for (int32_t h = ut; h < nhalf; h += 64 * kUpdWaves) {
-                    const int32_t blk = h >> 2;
-                    int32_t dist = blk - bk;
+                for (int32_t h = ut; h < nitem; h += 64 * kUpdWaves) {
+                    const int32_t col0 = h * kUpdCols;
+                    int32_t dist = (col0 >> 6) - bk;
                     if (dist < 0) dist += NB;
                     if (dist <= dskip) continue;   // dist 0: the flipped block itself
-                    const int32_t wi = h >> 1;
-                    const uint32_t shift = 16u * (uint32_t)(h & 1);
-                    int32_t accb[16];
+                    const int32_t wi = col0 >> 5;
+                    const uint32_t shift = (uint32_t)col0 & 31u;
+                    int32_t accb[kUpdCols];
 #pragma unroll
-                    for (int c = 0; c < 16; ++c) accb[c] = 0;
+                    for (int c = 0; c < kUpdCols; ++c) accb[c] = 0;
                     int32_t sum2 = 0;
                     for (int32_t f0 = 0; f0 < nf; f0 += 8) {
                         // eight independent row loads in flight: every load
@@ -346,13 +359,13 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                         for (int i = 0; i < 8; ++i) {
                             sum2 += s2v[i];
 #pragma unroll
-                            for (int c = 0; c < 16; ++c) accb[c] += (int32_t)((wv[i] >> c) & 1u) * s2v[i];
+                            for (int c = 0; c < kUpdCols; ++c) accb[c] += (int32_t)((wv[i] >> c) & 1u) * s2v[i];
                         }
                     }
                     // H_c += sum_f 2 s_f J_fc with J = 1 - 2 bit
 #pragma unroll
-                    for (int c = 0; c < 16; ++c) {
-                        const int32_t col = (h << 4) + c;
+                    for (int c = 0; c < kUpdCols; ++c) {
+                        const int32_t col = col0 + c;
                         if (col < n) L.H[col] += sum2 - 2 * accb[c];
                     }
                 }

@@ -65,7 +65,7 @@ struct Sl {
 
 struct VbLds {
     uint32_t* sp;                 // spins, VbLayout words
-    uint32_t* thr;                // [8][kTab]: 64 + x -> thr[x] >> 16; 0x10000 for x <= 0
+    uint32_t* thr;                // [8][kTab]: 64 - x -> thr[x] >> 16; 0x10000 for x <= 0
     unsigned long long* accs;     // [8]
     int32_t* flag;                // [4]: split units' abort flag
     int32_t* cls;                 // [kMaxCls + 1] first position of each colour class
@@ -160,8 +160,8 @@ __device__ __forceinline__ void load_ents(PE ent, Stage& st)
 
 // Metropolis decisions of one chunk for every chain, from the unsatisfied-bond
 // counts: chain c's count is the `width`-bit field of cA (c even or RPAD < 8)
-// or cB (c odd, RPAD 8) at bit fsh(c).  Returns, in lane j < 64 / P, spin
-// word j's flip mask; acc[c] += chain c's accepted flips.
+// or cB (c odd, RPAD 8) at bit fsh(c).  Returns this lane's flips in spin-word
+// form (chain c's flip at bit c P); acc[c] += chain c's accepted flips.
 template <int RPAD>
 __device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, const VbLds& L, const uint32_t* gx,
                                               uint32_t cA, uint32_t cB, bool wide, int32_t deg, bool act,
@@ -176,49 +176,51 @@ __device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, con
         const uint32_t fsh = RPAD == 8 ? (wide ? 8u * (uint32_t)(c >> 1) : 4u * (uint32_t)c) : (uint32_t)(c * S::P);
         return __builtin_amdgcn_ubfe(RPAD == 8 && (c & 1) ? cB : cA, fsh, width);
     };
-    // byte address of thr[c][64 + deg]; chain c's entry for its x = deg - 2 cnt
-    // is 8 cnt bytes below (plus c kTab words)
-    const int32_t tbase = (64 + deg) * 4;
+    // The table holds chain c's entry for x at word c kTab + 64 - x, so the
+    // entry for x = deg - 2 cnt is at byte 4 (64 - deg) + 8 cnt.
+    uint32_t tbase = (uint32_t)(64 - deg) * 4u;
+    asm volatile("" : "+v"(tbase));   // one register: each address is then a single shift-add
     const char* tb = (const char*)L.thr;
     const uint32_t hs = 16u * (hsel & 1u);
-    // lane j < 64 / P assembles spin word j of the chunk from the ballots
-    const uint32_t sel = (uint32_t)(lane * S::P) >> 5;   // which half of a ballot
-    const uint32_t off = (uint32_t)(lane * S::P) & 31u;  // bit offset inside that half
-    auto fold = [&](int c, unsigned long long m) -> uint32_t {
-        const uint32_t h = sel ? (uint32_t)(m >> 32) : (uint32_t)m;
-        return (S::P == 32 ? h : (h >> off) & ((1u << (S::P & 31)) - 1u)) << (c * S::P);
-    };
-    uint32_t word = 0, tie = 0;
+    const unsigned long long am = __builtin_amdgcn_ballot_w64(act);
+    uint32_t fl = 0;
+    bool tie = false;   // a lane mask: stays in scalar registers
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) {
         if (c < nch) {
-            const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + tbase - 8 * (int32_t)count(c));
+            const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (count(c) << 3) + tbase);
             const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
-            const unsigned long long m = __ballot(act && rh < th);
-            tie |= (act && rh == th) ? 1u << c : 0u;
+            const bool f = rh < th;
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(f) & am;
+            tie = tie || rh == th;
             acc[c] += (uint32_t)__popcll(m);
-            word |= fold(c, m);
+            fl |= (f && act) ? 1u << (c * S::P) : 0u;
         }
     }
-    if (__any(tie != 0u)) {
+    if ((__builtin_amdgcn_ballot_w64(tie) & am) != 0ull) {
         // A equals the high half of the threshold (those lanes did not flip
         // above): decide on the low half
 #pragma unroll
         for (int c = 0; c < RPAD; ++c) {
-            if (c < nch && __any((tie >> c) & 1u)) {
-                bool fl = false;
-                if ((tie >> c) & 1u) {
-                    const int32_t x = deg - 2 * (int32_t)count(c);
-                    const U4 Bk = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
-                    fl = half_word(Bk, hsel) < gl(&up->thr_lo[c][0])[x];
+            if (c < nch) {
+                const uint32_t cnt = count(c);
+                const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (cnt << 3) + tbase);
+                const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
+                const bool ti = act && rh == th;
+                if (__builtin_amdgcn_ballot_w64(ti) != 0ull) {
+                    bool f2 = false;
+                    if (ti) {
+                        const int32_t x = deg - 2 * (int32_t)cnt;
+                        const U4 Bk = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
+                        f2 = half_word(Bk, hsel) < gl(&up->thr_lo[c][0])[x];
+                    }
+                    acc[c] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(f2));
+                    fl |= f2 ? 1u << (c * S::P) : 0u;
                 }
-                const unsigned long long m = __ballot(fl);
-                acc[c] += (uint32_t)__popcll(m);
-                word |= fold(c, m);
             }
         }
     }
-    return word;
+    return fl;
 }
 
 // Updates the positions of one chunk for every chain of the unit.  acc[c]
@@ -267,16 +269,16 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
     }
 
     if (RPAD == 8 && !wide) cB = cA;
-    const uint32_t word = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key, acc);
-    // write the flips back: one lane per spin word of the chunk (a member of
-    // a split unit also writes the new word through to HBM)
-    if (lane < 64 / S::P && word) {
-        const uint32_t wi = ((uint32_t)(q - lane) >> S::LP) + (uint32_t)lane;
-        if (SPLIT) {
-            const uint32_t old = atomicXor(&L.sp[wi], word);
-            gl(up->state)[wi] = old ^ word;
-        } else {
-            atomicXor(&L.sp[wi], word);
+    const uint32_t fl = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key, acc);
+    // write the flips back: every lane XORs its flips into its spin word (the
+    // P lanes of a word are in this wavefront's chunk, nothing else writes it)
+    if (fl) atomicXor(&L.sp[(uint32_t)q >> S::LP], fl << qsh);
+    if (SPLIT) {
+        // a member of a split unit also writes the chunk's words through to HBM
+        wave_sync();
+        if (lane < 64 / S::P) {
+            const uint32_t wi = ((uint32_t)(q - lane) >> S::LP) + (uint32_t)lane;
+            if (wi < (uint32_t)up->state_words) gl(up->state)[wi] = L.sp[wi];
         }
     }
 }
@@ -406,9 +408,11 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
 
     const SG_G uint32_t* gstate = gl(up->state);
     for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = gstate[w];
+    // chain c's threshold high halves: word c kTab + j holds the entry for
+    // x = 64 - j (0x10000 for x <= 0: always accepted)
     for (int i = tid; i < kVbMaxChains * kTab; i += nthr) {
-        const int c = i / kTab, x = i - c * kTab - 64;
-        L.thr[i] = x <= 0 ? 0x10000u : gl(&up->thr_hi[c][0])[x];
+        const int c = i / kTab, x = 64 - (i - c * kTab);
+        L.thr[i] = x <= 0 ? 0x10000u : x < kVbXMax ? gl(&up->thr_hi[c][0])[x] : 0u;
     }
     if (tid < kVbMaxChains) {
         L.accs[tid] = 0;
