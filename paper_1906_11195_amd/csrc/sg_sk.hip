@@ -14,12 +14,12 @@
 //    previous block's rows restricted to this block's columns.
 //  * decider wavefront: lane i owns spin 64 b + i.  It corrects the block's
 //    fields for the flips of the previous block (previous-block tile), then
-//    decides the block speculatively: every lane compares x with xmax as if no
-//    earlier spin of the block flipped; a ballot finds the first flip j, lane j
-//    flips, every lane's field is patched with row j of the block tile, and the
-//    scan resumes at j + 1.  Decisions made with exact fields are final, so the
-//    result is the plain sequential sweep.  The block's flips are published to
-//    a ring buffer.
+//    decides the block in rounds: a lane whose decision cannot change
+//    whichever way the undecided lanes before it go (each moves its field by
+//    at most 2) is decided now, the first undecided lane always is, and the
+//    flips decided in a round patch the fields of the later lanes from row j
+//    of the block tile.  The result is exactly the plain sequential sweep.
+//    The block's flips are published to a ring buffer.
 //  * updater wavefronts: apply each published block's flips to all other fields
 //    (H_k += 2 s_j J_jk, rows read bit-packed, a few fields per lane), lagging one
 //    block behind; they skip the flipped block (patched in the decider) and the
@@ -43,11 +43,8 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 #ifndef SG_SK_RING
 #define SG_SK_RING 4
 #endif
-#ifndef SG_SK_WIN
-#define SG_SK_WIN 1
-#endif
 constexpr int kRing = SG_SK_RING;   // blocks in flight between the roles
-constexpr int kWin = SG_SK_WIN;     // previous blocks the decider corrects for itself
+constexpr int kWin = 1;             // previous blocks the decider corrects for itself
 constexpr int kTileWords = 2 + 2 * kWin;   // per lane: own-block row, kWin previous rows
 constexpr int kThrCache = 512;      // threshold entries cached in LDS
 #ifndef SG_SK_UPD
@@ -173,16 +170,18 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
 
     if (wave == 1) {
         // ---------------- prep ----------------
-        // coupling tiles (bit-packed, bit 1 = J -1), columns of block b: row
-        // 64 b + lane, then rows 64 (b - d) + lane for d = 1..DW; the tiles of
-        // the next block are loaded while this block's uniforms are drawn
+        // coupling tiles (bit-packed, bit 1 = J -1) of lane i's own row
+        // 64 b + i: its columns in block b, then in blocks b - d, d = 1..DW
+        // (J is symmetric, so bit j is the coupling of spin j of that block to
+        // spin i); the tiles of the next block are loaded while this block's
+        // uniforms are drawn
         uint32_t tw[2 * (kWin + 1)];
         auto load_tiles = [&](int32_t bq) {
-            const int32_t w0 = 2 * bq, w1 = 2 * bq + 1;
+            const int32_t rr = (bq << 6) + lane;
 #pragma unroll
             for (int d = 0; d <= kWin; ++d) {
                 const int32_t bb = bq - d < 0 ? bq - d + NB : bq - d;
-                const int32_t rr = (bb << 6) + lane;
+                const int32_t w0 = 2 * bb, w1 = 2 * bb + 1;
                 const bool live = d <= DW && rr < n;
                 tw[2 * d] = live ? Jb[(int64_t)rr * wn + w0] : 0u;
                 tw[2 * d + 1] = (live && w1 < wn) ? Jb[(int64_t)rr * wn + w1] : 0u;
@@ -244,6 +243,15 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         __builtin_amdgcn_s_setprio(3);
         uint32_t acc = 0;
         int32_t b = 0, s = 0, slot = 0;
+        // flips of the previous block: to spin +1 (bit 1 -> 0) and to -1
+        unsigned long long pFp = 0ull, pFn = 0ull;
+        const unsigned long long lt = (1ull << lane) - 1ull;   // lanes before this one
+        const unsigned long long gt = ~lt & ~(1ull << lane);   // lanes after it
+        // field change of this lane from flips F+ (to +1) and F- (to -1) with
+        // coupling bits row (bit j = 1: J = -1): sum over j of 2 s_j' J_jk
+        auto delta = [](unsigned long long fp, unsigned long long fn, unsigned long long row) -> int32_t {
+            return 2 * (__popcll(fp) - __popcll(fn)) - 4 * (__popcll(fp & row) - __popcll(fn & row));
+        };
         for (int64_t g = 0; g < total; ++g) {
             wait_ge(L, kPrepared, (int32_t)(g + 1), err);
             if (g > DW) wait_ge(L, kApplied, (int32_t)(g - DW), err);
@@ -251,48 +259,51 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             const bool act = p < n;
             const int32_t xm = L.xm[slot * 64 + lane];
             const uint32_t* tl = L.tile + ((size_t)slot * 64 + lane) * kTileWords;
-            const uint32_t d0 = tl[0], d1 = tl[1];
+            const unsigned long long D = ((unsigned long long)tl[1] << 32) | tl[0];   // own row, this block
             int32_t Hp = act ? L.H[p] : 0;
             uint32_t sb = act ? (L.bits[p >> 5] >> (p & 31)) & 1u : 0u;
-            const uint32_t sh = (uint32_t)lane & 31u;
-            // this block's fields still miss the flips of the previous DW blocks
-#pragma unroll
-            for (int d = 1; d <= kWin; ++d) {
-                if (d > DW || g - d < 0) break;
-                const uint32_t e0 = tl[2 * d], e1 = tl[2 * d + 1];
-                int ps = slot - d;
-                if (ps < 0) ps += kRing;
-                const int32_t nfp = L.nflip[ps];
-                // the block's flips in one LDS read (lane f holds flip f)
-                const int32_t fvl = L.flips[ps * 64 + lane];
-                for (int32_t f = 0; f < nfp; ++f) {
-                    const int32_t fv = __builtin_amdgcn_readlane(fvl, f);
-                    const int jf = fv & 63;
-                    const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)e0, jf)
-                                                 : (uint32_t)__builtin_amdgcn_readlane((int)e1, jf);
-                    const int32_t jv = ((w >> sh) & 1u) ? -1 : 1;
-                    Hp += (fv < 0 ? -2 : 2) * jv;
-                }
+            // this block's fields still miss the flips of the previous block
+            if (DW >= 1 && g >= 1) {
+                const unsigned long long C = ((unsigned long long)tl[3] << 32) | tl[2];   // own row, previous block
+                Hp += delta(pFp, pFn, C);
             }
-            int32_t start = 0, nf = 0, myflip = 0;   // lane f records flip f
-            for (;;) {
+            // Decisions in rounds.  A lane's decision is certain once it
+            // cannot change whichever way the undecided lanes before it go:
+            // each of them moves its field by at most 2.  The first undecided
+            // lane is always certain, so every round decides at least one lane
+            // (the exact sequential result, usually in one or two rounds).  The
+            // flips decided in a round change the fields of the lanes after
+            // them at once; after the last round every lane adds the flips
+            // after it.
+            unsigned long long SB = __builtin_amdgcn_ballot_w64(sb != 0u);
+            unsigned long long und = __builtin_amdgcn_ballot_w64(act);
+            unsigned long long Fp = 0ull, Fn = 0ull;
+            int32_t nf = 0;
+            while (und != 0ull) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(und >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)und, 0u));
+                const bool mine = (und >> lane) & 1ull;
                 const int32_t x = sb ? -Hp : Hp;
-                const bool flip = act && lane >= start && x <= xm;
-                const unsigned long long m = __ballot(flip);
-                if (m == 0ull) break;
-                const int j = __ffsll((long long)m) - 1;
-                const uint32_t nb = (uint32_t)__builtin_amdgcn_readlane((int)sb, j) ^ 1u;   // new bit of j
-                if (lane == j) sb = nb;
-                const uint32_t w = lane < 32 ? (uint32_t)__builtin_amdgcn_readlane((int)d0, j)
-                                             : (uint32_t)__builtin_amdgcn_readlane((int)d1, j);
-                const int32_t jv = ((w >> sh) & 1u) ? -1 : 1;
-                if (lane != j) Hp += (nb ? -2 : 2) * jv;
-                if (lane == nf) myflip = j | (int32_t)(nb << 31);
-                ++nf;
-                start = j + 1;
+                const int32_t slack = 2 * (int32_t)below;
+                const unsigned long long F = __builtin_amdgcn_ballot_w64(mine && x + slack <= xm);
+                const unsigned long long K = __builtin_amdgcn_ballot_w64(mine && x - slack > xm);
+                und &= ~(F | K);
+                const unsigned long long fp = F & SB, fn = F & ~SB;
+                Hp += delta(fp & lt, fn & lt, D);
+                if ((F >> lane) & 1ull) {
+                    // flip entry: local row | (new spin -1) << 31, in lane order
+                    L.flips[slot * 64 + nf + __popcll(F & lt)] = lane | (int32_t)((sb ^ 1u) << 31);
+                    sb ^= 1u;
+                }
+                nf += __popcll(F);
+                SB ^= F;
+                Fp |= fp;
+                Fn |= fn;
             }
+            Hp += delta(Fp & gt, Fn & gt, D);
+            pFp = Fp;
+            pFn = Fn;
             if (act) L.H[p] = Hp;
-            if (lane < nf) L.flips[slot * 64 + lane] = myflip;
             const unsigned long long mask = __ballot(sb != 0u);
             if (lane == 0) {
                 L.bits[2 * b] = (uint32_t)mask;
