@@ -29,6 +29,8 @@ if ROOT not in sys.path:
 
 METRIC = "spin flips/ns at 1 GPU (VB, SK), batched vs plain; p50/p99 run latency"
 HBM_PEAK_GBS = 8000.0
+HBM_PEAK_BPS = HBM_PEAK_GBS * 1e9
+MFMA_INT8_PEAK_OPS = 5.0e15   # dense int8 MFMA, MI355X
 
 
 def log(msg):
@@ -191,10 +193,22 @@ def run_sk(args, torch, sg, workloads):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     sg.sg_free(ctx)
-    upd = 64 * 2 * 4096 * args.sk_sweeps
+    n, reps, period = 4096, 2, descs[0].recompute_period
+    upd = 64 * reps * n * args.sk_sweeps
+    acc = float(res["accepted"].sum() - a0) / upd
+    rate = upd / el
+    # algorithmic HBM bytes per attempted update: one bit-packed coupling row
+    # per accepted flip (a N / 8) plus the int8 J read by the exact recompute
+    # once per sample and period (N^2 / (period N R)); int8 MFMA work of the
+    # recompute: 2 N^2 R per sample and period (2 N / period per update)
+    hbm = rate * (acc * n / 8 + n / (period * reps))
+    mfma = rate * 2.0 * n / period
     return dict(workload="SK: 64 samples x 2 replicas, N=4096, T=0.5, sweeps 64..%d" % (64 + args.sk_sweeps),
-                updates_per_ns=upd / (el * 1e9),
-                accepted_fraction=float(res["accepted"].sum() - a0) / upd, sweeps=args.sk_sweeps)
+                updates_per_ns=rate / 1e9, accepted_fraction=acc, sweeps=args.sk_sweeps,
+                roofline={"bound": "latency", "hbm_GBps": round(hbm / 1e9, 1),
+                          "hbm_frac": round(hbm / HBM_PEAK_BPS, 4),
+                          "mfma_int8_TOPs": round(mfma / 1e12, 3),
+                          "mfma_frac": round(mfma / MFMA_INT8_PEAK_OPS, 6)})
 
 
 def run_uneven(args, torch, sg, workloads):

@@ -10,27 +10,31 @@
 //    acceptance uniform r of every position of the block (two Philox streams)
 //    and turns it into xmax = max{x : r < thr[x]}, so that a spin with
 //    x = s_i H_i flips iff x <= xmax; it also fetches, from the bit-packed
-//    couplings, the 64 x 64 tile of the block's own rows and the tile of the
-//    previous block's rows restricted to this block's columns.
+//    couplings, lane i's own row 64 b + i restricted to the columns of block b
+//    and of the kWin blocks before it (J is symmetric: these are the
+//    couplings of those blocks' spins to spin i).
 //  * decider wavefront: lane i owns spin 64 b + i.  It corrects the block's
-//    fields for the flips of the previous block (previous-block tile), then
-//    decides the block in rounds: a lane whose decision cannot change
-//    whichever way the undecided lanes before it go (each moves its field by
-//    at most 2) is decided now, the first undecided lane always is, and the
-//    flips decided in a round patch the fields of the later lanes from row j
-//    of the block tile.  The result is exactly the plain sequential sweep.
-//    The block's flips are published to a ring buffer.
+//    fields for the flips of the previous kWin blocks (masked popcounts of
+//    their flip masks against its own row), then decides the block in rounds:
+//    a lane whose decision cannot change whichever way the undecided lanes
+//    before it go (each moves its field by at most 2) is decided now, the
+//    first undecided lane always is, and the flips decided in a round change
+//    the fields of the later lanes by masked popcounts against the own-block
+//    row.  The result is exactly the plain sequential sweep.  The block's
+//    flips are published to a ring buffer.
 //  * updater wavefronts: apply each published block's flips to all other fields
-//    (H_k += 2 s_j J_jk, rows read bit-packed, a few fields per lane), lagging one
-//    block behind; they skip the flipped block (patched in the decider) and the
-//    next block (corrected by the decider from its tile), except for the last
-//    block of a launch.
+//    (H_k += 2 s_j J_jk, rows read bit-packed, a few fields per lane), up to
+//    kWin blocks behind the decider; they skip the flipped block (patched in
+//    the decider) and the next kWin blocks (corrected by the decider), except
+//    for blocks decided after the end of the launch.
 //
 // Every `period` sweeps the fields are recomputed exactly as H = J S with int8
 // MFMA (v_mfma_i32_16x16x64_i8, int32 accumulation) and compared with the
 // incremental ones; a mismatch raises the context's error flag.  Bond sums
 // B = (1/2) s^T J s of the snapshots are computed the same way at measurement
 // time.
+#include <type_traits>
+
 #include "sg_internal.h"
 #include "sg_philox.h"
 
@@ -43,19 +47,22 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 #ifndef SG_SK_RING
 #define SG_SK_RING 4
 #endif
+#ifndef SG_SK_WIN
+#define SG_SK_WIN 1
+#endif
 constexpr int kRing = SG_SK_RING;   // blocks in flight between the roles
-constexpr int kWin = 1;             // previous blocks the decider corrects for itself
+constexpr int kWin = SG_SK_WIN;     // previous blocks the decider corrects for itself
 constexpr int kTileWords = 2 + 2 * kWin;   // per lane: own-block row, kWin previous rows
 constexpr int kThrCache = 512;      // threshold entries cached in LDS
 #ifndef SG_SK_UPD
 #define SG_SK_UPD 8
 #endif
-#ifndef SG_SK_COLS
-#define SG_SK_COLS 8
+#ifndef SG_SK_UPB
+#define SG_SK_UPB 1
 #endif
 constexpr int kUpdWaves = SG_SK_UPD;   // updater wavefronts
-constexpr int kUpdCols = SG_SK_COLS;   // fields one updater lane owns (4, 8 or 16)
-static_assert(kUpdCols == 4 || kUpdCols == 8 || kUpdCols == 16, "updater item width");
+constexpr int kUpdBlocks = SG_SK_UPB;  // decided blocks an updater pass takes at most
+static_assert(kUpdBlocks >= 1 && kUpdBlocks <= kRing, "updater pass width");
 constexpr int kSkThreads = 64 * (2 + kUpdWaves);
 constexpr int kSpinLimit = 1 << 22; // bounded waits: a stuck pipeline aborts
 static_assert(kRing >= kWin + 1, "flip batches must outlive the correction window");
@@ -67,9 +74,10 @@ struct SkLds {
     int32_t* xm;                // [kRing][64]
     uint32_t* tile;             // [kRing][64][kTileWords]
     int32_t* flips;             // [kRing][64]: local row | (new spin -1) << 31
-    int32_t* nflip;             // [kRing]
-    int32_t* sync;              // decided, applied, prepared, abort, done[kRing]
+    int32_t* nflip;             // [kRing]: flips | flips to +1 << 8
+    int32_t* sync;              // decided, prepared, abort, progress[kUpdWaves]
     uint4* pr;                  // [64] Philox blocks of the prep's current 4 spin blocks
+    unsigned long long* spr;    // [512] byte-spread table of the updaters
 };
 
 __device__ __forceinline__ SkLds sk_carve(uint8_t* base, int32_t n, int32_t wn)
@@ -88,12 +96,13 @@ __device__ __forceinline__ SkLds sk_carve(uint8_t* base, int32_t n, int32_t wn)
     L.tile = (uint32_t*)take((size_t)kRing * 64 * kTileWords * 4);
     L.flips = (int32_t*)take((size_t)kRing * 64 * 4);
     L.nflip = (int32_t*)take((size_t)kRing * 4);
-    L.sync = (int32_t*)take((size_t)(4 + kRing) * 4);
+    L.sync = (int32_t*)take((size_t)(3 + kUpdWaves) * 4);
     L.pr = (uint4*)take(64 * 16);
+    L.spr = (unsigned long long*)take(512 * 8);
     return L;
 }
 
-enum { kDecided = 0, kApplied = 1, kPrepared = 2, kAbort = 3, kDone = 4 };
+enum { kDecided = 0, kPrepared = 1, kAbort = 2, kProg = 3 };
 
 __device__ __forceinline__ int ld_acq(int32_t* p)
 {
@@ -105,20 +114,39 @@ __device__ __forceinline__ void st_rel(int32_t* p, int32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Waits (whole wavefront) until *p >= target.  After kSpinLimit polls the
-// pipeline is declared stuck: the abort flag releases every other wait and
-// the context's error flag reports it.
+// One poll of a wait that has not been met yet: true when the wait must end
+// without its condition (abort raised, or this wait was the one that ran out
+// of polls: after kSpinLimit polls the pipeline is declared stuck, the abort
+// flag releases every other wait and the context's error flag reports it).
+__device__ __forceinline__ bool wait_giveup(const SkLds& L, int& spins, int* err)
+{
+    if (ld_acq(&L.sync[kAbort])) return true;
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+        st_rel(&L.sync[kAbort], 1);
+        atomicOr(err, 2);
+        return true;
+    }
+    return false;
+}
+
+// Waits (whole wavefront) until *p >= target.
 __device__ __forceinline__ void wait_ge(const SkLds& L, int32_t idx, int32_t target, int* err)
 {
     int spins = 0;
     while (ld_acq(&L.sync[idx]) < target) {
-        if (ld_acq(&L.sync[kAbort])) return;
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-            st_rel(&L.sync[kAbort], 1);
-            atomicOr(err, 2);
-            return;
-        }
+        if (wait_giveup(L, spins, err)) return;
+    }
+}
+
+// Waits (whole wavefront) until every updater wavefront has applied the
+// first `target` blocks of the launch (lane w reads wavefront w's progress).
+__device__ __forceinline__ void wait_applied(const SkLds& L, int32_t target, int* err)
+{
+    const int lane = threadIdx.x & 63;
+    int spins = 0;
+    while (__builtin_amdgcn_ballot_w64(lane < kUpdWaves && ld_acq(&L.sync[kProg + lane]) < target) != 0ull) {
+        if (wait_giveup(L, spins, err)) return;
     }
 }
 
@@ -157,7 +185,14 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
     for (int32_t i = tid; i < n; i += nthr) L.H[i] = gl(ch->H)[i];
     for (int32_t w = tid; w < wn + 2; w += nthr) L.bits[w] = w < wn ? gl(ch->state)[w] : 0u;
     for (int32_t x = tid; x < cached; x += nthr) L.thr[x] = gl(ch->thr)[x];
-    if (tid < 4 + kRing) L.sync[tid] = 0;
+    if (tid < 3 + kUpdWaves) L.sync[tid] = 0;
+    for (int e = tid; e < 512; e += nthr) {
+        // byte c of entry b + 256 m: bit c of b, in the low nibble (m = 0) or
+        // the high nibble (m = 1)
+        unsigned long long v = 0ull;
+        for (int c = 0; c < 8; ++c) v |= (unsigned long long)((e >> c) & 1) << (8 * c + 4 * (e >> 8));
+        L.spr[e] = v;
+    }
     __syncthreads();
 
     const int32_t NB = (n + 63) >> 6;
@@ -180,9 +215,9 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             const int32_t rr = (bq << 6) + lane;
 #pragma unroll
             for (int d = 0; d <= kWin; ++d) {
-                const int32_t bb = bq - d < 0 ? bq - d + NB : bq - d;
+                const bool live = d <= DW && rr < n;   // d <= DW < NB: one wrap at most
+                const int32_t bb = !live ? 0 : (bq - d < 0 ? bq - d + NB : bq - d);
                 const int32_t w0 = 2 * bb, w1 = 2 * bb + 1;
-                const bool live = d <= DW && rr < n;
                 tw[2 * d] = live ? Jb[(int64_t)rr * wn + w0] : 0u;
                 tw[2 * d + 1] = (live && w1 < wn) ? Jb[(int64_t)rr * wn + w1] : 0u;
             }
@@ -225,8 +260,17 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                 const float xf = lv / slope;
                 x0 = xf >= (float)(ch->thr_len - 1) ? ch->thr_len - 1 : (xf <= 0.0f ? 0 : (int32_t)xf);
             }
-            while (x0 > 0 && !((unsigned long long)r < thr_at(L, ch, cached, x0))) --x0;
-            while (x0 + 1 < ch->thr_len && (unsigned long long)r < thr_at(L, ch, cached, x0 + 1)) ++x0;
+            // (entries cached in LDS first; a long table's tail is read from
+            // HBM on a path of its own, so that the common path holds no
+            // wait for this wavefront's outstanding loads)
+            if (x0 < cached) {
+                while (x0 > 0 && !((unsigned long long)r < L.thr[x0])) --x0;
+                while (x0 + 1 < cached && (unsigned long long)r < L.thr[x0 + 1]) ++x0;
+            }
+            if (x0 + 1 >= cached && cached < ch->thr_len) {
+                while (x0 > 0 && !((unsigned long long)r < thr_at(L, ch, cached, x0))) --x0;
+                while (x0 + 1 < ch->thr_len && (unsigned long long)r < thr_at(L, ch, cached, x0 + 1)) ++x0;
+            }
             L.xm[slot * 64 + lane] = x0;
             wave_release();
             if (lane == 0) st_rel(&L.sync[kPrepared], (int32_t)(g + 1));
@@ -243,8 +287,11 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         __builtin_amdgcn_s_setprio(3);
         uint32_t acc = 0;
         int32_t b = 0, s = 0, slot = 0;
-        // flips of the previous block: to spin +1 (bit 1 -> 0) and to -1
-        unsigned long long pFp = 0ull, pFn = 0ull;
+        // flips of the previous kWin blocks (d = 0: the block before this
+        // one): to spin +1 (bit 1 -> 0) and to -1
+        unsigned long long pFp[kWin], pFn[kWin];
+#pragma unroll
+        for (int d = 0; d < kWin; ++d) pFp[d] = pFn[d] = 0ull;
         const unsigned long long lt = (1ull << lane) - 1ull;   // lanes before this one
         const unsigned long long gt = ~lt & ~(1ull << lane);   // lanes after it
         // field change of this lane from flips F+ (to +1) and F- (to -1) with
@@ -254,18 +301,24 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         };
         for (int64_t g = 0; g < total; ++g) {
             wait_ge(L, kPrepared, (int32_t)(g + 1), err);
-            if (g > DW) wait_ge(L, kApplied, (int32_t)(g - DW), err);
+            // the prep's outputs and the spins (written by this wavefront
+            // only) are read before waiting for the updaters
             const int32_t p = (b << 6) + lane;
             const bool act = p < n;
             const int32_t xm = L.xm[slot * 64 + lane];
             const uint32_t* tl = L.tile + ((size_t)slot * 64 + lane) * kTileWords;
             const unsigned long long D = ((unsigned long long)tl[1] << 32) | tl[0];   // own row, this block
-            int32_t Hp = act ? L.H[p] : 0;
             uint32_t sb = act ? (L.bits[p >> 5] >> (p & 31)) & 1u : 0u;
-            // this block's fields still miss the flips of the previous block
-            if (DW >= 1 && g >= 1) {
-                const unsigned long long C = ((unsigned long long)tl[3] << 32) | tl[2];   // own row, previous block
-                Hp += delta(pFp, pFn, C);
+            if (g > DW) wait_applied(L, (int32_t)(g - DW), err);
+            int32_t Hp = act ? L.H[p] : 0;
+            // this block's fields still miss the flips of the previous DW
+            // blocks (own row restricted to block b - d, d = 1..DW)
+#pragma unroll
+            for (int d = 1; d <= kWin; ++d) {
+                if (d <= DW && g >= d) {
+                    const unsigned long long C = ((unsigned long long)tl[2 * d + 1] << 32) | tl[2 * d];
+                    Hp += delta(pFp[d - 1], pFn[d - 1], C);
+                }
             }
             // Decisions in rounds.  A lane's decision is certain once it
             // cannot change whichever way the undecided lanes before it go:
@@ -301,14 +354,19 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                 Fn |= fn;
             }
             Hp += delta(Fp & gt, Fn & gt, D);
-            pFp = Fp;
-            pFn = Fn;
+#pragma unroll
+            for (int d = kWin - 1; d > 0; --d) {
+                pFp[d] = pFp[d - 1];
+                pFn[d] = pFn[d - 1];
+            }
+            pFp[0] = Fp;
+            pFn[0] = Fn;
             if (act) L.H[p] = Hp;
             const unsigned long long mask = __ballot(sb != 0u);
             if (lane == 0) {
                 L.bits[2 * b] = (uint32_t)mask;
                 if (2 * b + 1 < wn) L.bits[2 * b + 1] = (uint32_t)(mask >> 32);
-                L.nflip[slot] = nf;
+                L.nflip[slot] = nf | (__popcll(Fp) << 8);
                 acc += (uint32_t)nf;
             }
             wave_release();
@@ -327,71 +385,156 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         if (lane == 0 && acc) atomicAdd(ch->accepted, (unsigned long long)acc);
     } else {
         // ---------------- updaters ----------------
-        // updater lane items: kUpdCols consecutive fields (one slice of a
-        // coupling-row word)
-        const int ut = tid - 128;
-        const int32_t nitem = (n + kUpdCols - 1) / kUpdCols;
+        // An updater lane owns items of 8 consecutive fields (one byte of a
+        // coupling-row word).  L.spr spreads the row byte of a flip over the
+        // bytes of a 64-bit word: bit c goes to byte c, in its low nibble for a
+        // flip to +1 and its high nibble for a flip to -1, so one 64-bit add
+        // per flip counts the couplings of all 8 fields (8 flips per batch:
+        // no nibble overflows).  A wavefront takes every decided block it
+        // finds, up to kUpdBlocks, in one pass: their row loads share one
+        // memory latency.  Its progress word tells the decider how many blocks
+        // of the launch it has applied.
+        const int uw = wave - 2;   // updater index
+        const int ut = uw * 64 + lane;
+        const int32_t nitem = (n + 7) >> 3;
+        const char* sprb = (const char*)L.spr;
         int32_t bk = 0, slot = 0;
-        for (int64_t k = 0; k < total; ++k) {
+        for (int64_t k = 0; k < total;) {
             wait_ge(L, kDecided, (int32_t)(k + 1), err);
-            const int32_t nf = L.nflip[slot];
-            // blocks bk + d (1 <= d <= DW) decided later in this launch get
-            // this batch from the decider's correction
-            const int32_t dskip = (int32_t)min((int64_t)DW, total - 1 - k);
-            if (nf > 0) {
+            int32_t np = 1;
+            if (kUpdBlocks > 1) {
+                const int32_t dec = __builtin_amdgcn_readfirstlane(ld_acq(&L.sync[kDecided]));
+                np = (int32_t)max((int64_t)1, min((int64_t)kUpdBlocks, min((int64_t)dec, total) - k));
+            }
+            // per block j of the pass: ring slot, block index, first flip in
+            // the concatenated list, sum of 2 s' over its flips, and the
+            // blocks after it whose columns the decider corrects itself
+            int32_t sl[kUpdBlocks], bq[kUpdBlocks], cum[kUpdBlocks + 1], s2[kUpdBlocks], dsk[kUpdBlocks];
+            cum[0] = 0;
+#pragma unroll
+            for (int j = 0; j < kUpdBlocks; ++j) {
+                sl[j] = j == 0 ? slot : (sl[j - 1] + 1 == kRing ? 0 : sl[j - 1] + 1);
+                bq[j] = j == 0 ? bk : (bq[j - 1] + 1 == NB ? 0 : bq[j - 1] + 1);
+                const int32_t w = j < np ? __builtin_amdgcn_readfirstlane(L.nflip[sl[j]]) : 0;
+                const int32_t nfj = w & 0xff;
+                cum[j + 1] = cum[j] + nfj;
+                s2[j] = 2 * (2 * (w >> 8) - nfj);
+                dsk[j] = (int32_t)min((int64_t)DW, total - 1 - (k + j));
+            }
+            const int32_t ntot = cum[kUpdBlocks];
+            if (ntot > 0) {
                 for (int32_t h = ut; h < nitem; h += 64 * kUpdWaves) {
-                    const int32_t col0 = h * kUpdCols;
-                    int32_t dist = (col0 >> 6) - bk;
-                    if (dist < 0) dist += NB;
-                    if (dist <= dskip) continue;   // dist 0: the flipped block itself
+                    const int32_t col0 = h << 3;
+                    // the item takes a block's flips unless it lies in the
+                    // flipped block (patched in the decider) or in one of the
+                    // next dsk blocks (corrected by the decider)
+                    bool use[kUpdBlocks];
+                    bool any = false;
+                    int32_t sum2 = 0;
+#pragma unroll
+                    for (int j = 0; j < kUpdBlocks; ++j) {
+                        int32_t dist = (col0 >> 6) - bq[j];
+                        if (dist < 0) dist += NB;
+                        use[j] = j < np && dist > dsk[j];
+                        any = any || use[j];
+                        sum2 += use[j] ? s2[j] : 0;
+                    }
+                    if (!any) continue;
                     const int32_t wi = col0 >> 5;
                     const uint32_t shift = (uint32_t)col0 & 31u;
-                    int32_t accb[kUpdCols];
+                    int32_t dlt[8];   // per field: flips to +1 minus flips to -1 with coupling bit 1
 #pragma unroll
-                    for (int c = 0; c < kUpdCols; ++c) accb[c] = 0;
-                    int32_t sum2 = 0;
-                    for (int32_t f0 = 0; f0 < nf; f0 += 8) {
-                        // eight independent row loads in flight: every load
-                        // is issued (entries past the last flip re-read the
-                        // last flip's row and are weighted 0), so no load
-                        // sits behind a branch that waits for the one before
-                        uint32_t wv[8];
-                        int32_t s2v[8];
+                    for (int c = 0; c < 8; ++c) dlt[c] = 0;
+                    // One batch: NL row loads in flight, all issued before any
+                    // is used (the NL flip entries are read from LDS first, so
+                    // their latencies overlap too); entries past the last flip
+                    // re-read its row with a zero-width byte.  Batches of 16
+                    // when more than 8 flips are left, so that a block with up
+                    // to 16 flips costs one memory latency.
+                    auto batch = [&](int32_t f0, auto nlc) {
+                        constexpr int NL = decltype(nlc)::value;
+                        uint32_t wv[NL], wd[NL], tb[NL];
+                        int32_t fe[NL], rb[NL];
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const bool live = f0 + i < nf;
-                            const int32_t fv = L.flips[slot * 64 + min(f0 + i, nf - 1)];
-                            s2v[i] = live ? (fv < 0 ? -2 : 2) : 0;
-                            wv[i] = Jb[(int64_t)((bk << 6) + (fv & 63)) * wn + wi];
+                        for (int i = 0; i < NL; ++i) {
+                            const int32_t fi = min(f0 + i, ntot - 1);
+                            int32_t slj = sl[0], bqj = bq[0], cj = 0;
+                            bool uj = use[0];
+#pragma unroll
+                            for (int j = 1; j < kUpdBlocks; ++j) {
+                                if (fi >= cum[j]) {
+                                    slj = sl[j];
+                                    bqj = bq[j];
+                                    cj = cum[j];
+                                    uj = use[j];
+                                }
+                            }
+                            fe[i] = L.flips[slj * 64 + fi - cj];
+                            rb[i] = bqj << 6;
+                            wd[i] = (f0 + i < ntot && uj) ? 8u : 0u;
                         }
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) wv[i] >>= shift;
+                        for (int i = 0; i < NL; ++i) {
+                            const int32_t fv = __builtin_amdgcn_readfirstlane(fe[i]);
+                            tb[i] = fv < 0 ? 2048u : 0u;
+                            wv[i] = Jb[(int64_t)(rb[i] + (fv & 63)) * wn + wi];
+                        }
+                        // nibble counts of 8 flips at a time (at most 8: no carry)
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            sum2 += s2v[i];
+                        for (int i0 = 0; i0 < NL; i0 += 8) {
+                            unsigned long long acc = 0ull;
 #pragma unroll
-                            for (int c = 0; c < kUpdCols; ++c) accb[c] += (int32_t)((wv[i] >> c) & 1u) * s2v[i];
+                            for (int i = i0; i < i0 + 8; ++i) {
+                                const uint32_t byte = __builtin_amdgcn_ubfe(wv[i], shift, wd[i]);
+                                acc += *(const unsigned long long*)(sprb + tb[i] + (byte << 3));
+                            }
+                            const uint32_t lo = (uint32_t)acc, hi = (uint32_t)(acc >> 32);
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                dlt[c] += (int32_t)__builtin_amdgcn_ubfe(lo, 8u * c, 4u) -
+                                          (int32_t)__builtin_amdgcn_ubfe(lo, 8u * c + 4u, 4u);
+                                dlt[c + 4] += (int32_t)__builtin_amdgcn_ubfe(hi, 8u * c, 4u) -
+                                              (int32_t)__builtin_amdgcn_ubfe(hi, 8u * c + 4u, 4u);
+                            }
+                        }
+                    };
+                    for (int32_t f0 = 0; f0 < ntot;) {
+                        if (ntot - f0 > 8) {
+                            batch(f0, std::integral_constant<int, 16>{});
+                            f0 += 16;
+                        } else {
+                            batch(f0, std::integral_constant<int, 8>{});
+                            f0 += 8;
                         }
                     }
-                    // H_c += sum_f 2 s_f J_fc with J = 1 - 2 bit
+                    // H_c += sum over flips of 2 s' J_fc, J = 1 - 2 bit
+                    if (col0 + 8 <= n) {
+                        int4* hp = (int4*)(L.H + col0);
+                        int4 u0 = hp[0], u1 = hp[1];
+                        u0.x += sum2 - 4 * dlt[0];
+                        u0.y += sum2 - 4 * dlt[1];
+                        u0.z += sum2 - 4 * dlt[2];
+                        u0.w += sum2 - 4 * dlt[3];
+                        u1.x += sum2 - 4 * dlt[4];
+                        u1.y += sum2 - 4 * dlt[5];
+                        u1.z += sum2 - 4 * dlt[6];
+                        u1.w += sum2 - 4 * dlt[7];
+                        hp[0] = u0;
+                        hp[1] = u1;
+                    } else {
 #pragma unroll
-                    for (int c = 0; c < kUpdCols; ++c) {
-                        const int32_t col = col0 + c;
-                        if (col < n) L.H[col] += sum2 - 2 * accb[c];
+                        for (int c = 0; c < 8; ++c)
+                            if (col0 + c < n) L.H[col0 + c] += sum2 - 4 * dlt[c];
                     }
                 }
             }
             wave_release();
-            if (lane == 0) {
-                const int old = __hip_atomic_fetch_add(&L.sync[kDone + slot], 1, __ATOMIC_ACQ_REL,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (old == kUpdWaves - 1) {
-                    L.sync[kDone + slot] = 0;
-                    st_rel(&L.sync[kApplied], (int32_t)(k + 1));
-                }
-            }
-            if (++slot == kRing) slot = 0;
-            bk = bk + 1 == NB ? 0 : bk + 1;
+            k += np;
+            if (lane == 0) st_rel(&L.sync[kProg + uw], (int32_t)k);
+            slot += np;
+            if (slot >= kRing) slot -= kRing;
+            bk += np;
+            while (bk >= NB) bk -= NB;
         }
     }
     __syncthreads();
@@ -549,7 +692,7 @@ size_t sk_lds_bytes(int32_t n)
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return r16((size_t)n * 4) + r16((wn + 2) * 4) + r16((size_t)kThrCache * 8) + r16(kRing * 64 * 4) +
            r16((size_t)kRing * 64 * kTileWords * 4) + r16(kRing * 64 * 4) + r16(kRing * 4) +
-           r16((4 + kRing) * 4) + 64 * 16;
+           r16((3 + kUpdWaves) * 4) + 64 * 16 + 512 * 8;
 }
 
 int sk_threads() { return kSkThreads; }
