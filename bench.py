@@ -241,7 +241,7 @@ def run_serving(args, torch, sg, workloads):
     rng_len = [256, 512, 1024]
     for i, r in enumerate(reqs):
         r.sweeps = rng_len[i % 3]
-    server = serving.AgingServer(hbm_budget=64 << 30, max_active=64, chunk_sweeps=256, n_streams=4,
+    server = serving.AgingServer(hbm_budget=64 << 30, max_active=64, chunk_sweeps=256, n_streams=8,
                                  flags=sg.MEASURE_OBS)
     t0 = time.perf_counter()
     results = server.run(reqs, max_wall=120.0)

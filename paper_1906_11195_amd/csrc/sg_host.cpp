@@ -74,8 +74,23 @@ void er_generate(VbGraph& g, int64_t m, uint64_t seed, uint32_t graph_id)
     g.eu.resize((size_t)m);
     g.ev.resize((size_t)m);
     g.J.resize((size_t)m);
-    std::unordered_set<uint64_t> seen;
-    seen.reserve((size_t)m * 2 + 16);
+    // accepted pairs in an open-addressing set (linear probing, at most a
+    // quarter full; ~0 marks a free slot, no pair key has all bits set)
+    size_t cap = 16;
+    while (cap < (size_t)m * 4) cap <<= 1;
+    std::vector<uint64_t> seen(cap, ~0ull);
+    const int shift = 64 - __builtin_ctzll((unsigned long long)cap);
+    auto insert = [&](uint64_t key) {
+        size_t i = (size_t)((key * 0x9E3779B97F4A7C15ull) >> shift);
+        for (;;) {
+            if (seen[i] == ~0ull) {
+                seen[i] = key;
+                return true;
+            }
+            if (seen[i] == key) return false;
+            i = (i + 1) & (cap - 1);
+        }
+    };
     int64_t k = 0;
     for (uint64_t a = 0; k < m; ++a) {
         const U4 w = philox_stream(seed, (uint32_t)a, (uint32_t)(a >> 32), kDomGraph, 0u, graph_id);
@@ -83,7 +98,7 @@ void er_generate(VbGraph& g, int64_t m, uint64_t seed, uint32_t graph_id)
         const uint64_t v = ((uint64_t)w.y * n) >> 32;
         if (u == v) continue;
         const uint64_t key = u < v ? (u << 32) | v : (v << 32) | u;
-        if (!seen.insert(key).second) continue;
+        if (!insert(key)) continue;
         g.eu[(size_t)k] = (int32_t)u;
         g.ev[(size_t)k] = (int32_t)v;
         g.J[(size_t)k] = (w.z & 1u) ? (int8_t)-1 : (int8_t)1;
@@ -320,7 +335,21 @@ struct sg_ctx {
     void* user = nullptr;
     void* arena = nullptr;
     size_t arena_bytes = 0;
-    hipStream_t last_stream = nullptr;
+    // every stream a call has put this context's work on (synchronised, with
+    // the legacy stream of the set-up work, before the memory is released;
+    // never the whole device, so that other contexts keep running)
+    std::vector<hipStream_t> streams_used;
+    void note_stream(hipStream_t s)
+    {
+        for (hipStream_t x : streams_used)
+            if (x == s) return;
+        streams_used.push_back(s);
+    }
+    void sync_own()
+    {
+        (void)hipStreamSynchronize(nullptr);
+        for (hipStream_t x : streams_used) (void)hipStreamSynchronize(x);
+    }
     int32_t count = 0, R = 0, K = 0, n_chains = 0;
     int64_t t_max = 0, t_done = 0;
     std::vector<int64_t> times;
@@ -953,7 +982,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     }
     hip_check(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
     c->use_graph = o && (o->flags & SG_OPT_GRAPH);
-    hip_check(hipDeviceSynchronize());
+    // the set-up work ran on the legacy stream: wait for it alone
+    hip_check(hipStreamSynchronize(nullptr));
     if (o && (o->flags & SG_OPT_AUTOTUNE) && !o->threads_per_unit) vb_autotune(c);
 }
 
@@ -1011,11 +1041,13 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     }
 
     Arena A;
-    std::vector<size_t> off_J(jrep.size()), off_Jb(jrep.size());
+    std::vector<size_t> off_J(jrep.size()), off_Jb(jrep.size()), off_Jt(jrep.size());
+    const int tile_words = sk_tile_words();
     for (size_t j = 0; j < jrep.size(); ++j) {
         const int64_t n = d[jrep[j]].n;
         off_J[j] = A.take((size_t)(n * n));
         off_Jb[j] = A.take((size_t)n * (size_t)((n + 31) / 32) * 4);
+        off_Jt[j] = A.take((size_t)((n + 63) / 64) * 64 * (size_t)tile_words * 4);
     }
     std::vector<size_t> off_thr((size_t)count);
     for (int32_t i = 0; i < count; ++i) off_thr[(size_t)i] = A.take(thr[(size_t)i].size() * 8);
@@ -1065,6 +1097,24 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
             for (int64_t k = 0; k < n; ++k)
                 if (src[i * n + k] < 0) Jb[(size_t)(i * wn + (k >> 5))] |= 1u << (k & 31);
         hip_check(hipMemcpy(c->at<void>(off_Jb[j]), Jb.data(), Jb.size() * 4, hipMemcpyHostToDevice));
+        // the decider's tiles: row 64 b + l, words 2 bb and 2 bb + 1 for
+        // bb = b - d (cyclic), d = 0..DW with DW = min(window, blocks - 1)
+        const int64_t nb = (n + 63) / 64;
+        const int64_t dw = std::min<int64_t>(sk_window(), nb - 1);
+        std::vector<uint32_t> Jt((size_t)(nb * 64 * tile_words), 0u);
+        for (int64_t b = 0; b < nb; ++b)
+            for (int64_t l = 0; l < 64; ++l) {
+                const int64_t row = 64 * b + l;
+                if (row >= n) continue;
+                for (int64_t dd = 0; dd <= dw; ++dd) {
+                    const int64_t bb = (b - dd + nb) % nb;
+                    for (int64_t h = 0; h < 2; ++h) {
+                        const int64_t w = 2 * bb + h;
+                        if (w < wn) Jt[(size_t)((b * 64 + l) * tile_words + 2 * dd + h)] = Jb[(size_t)(row * wn + w)];
+                    }
+                }
+            }
+        hip_check(hipMemcpy(c->at<void>(off_Jt[j]), Jt.data(), Jt.size() * 4, hipMemcpyHostToDevice));
     });
     for (int32_t i = 0; i < count; ++i)
         hip_check(hipMemcpy(c->at<void>(off_thr[(size_t)i]), thr[(size_t)i].data(), thr[(size_t)i].size() * 8,
@@ -1081,6 +1131,7 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
             std::memset(&S, 0, sizeof(S));
             S.J = c->at<int8_t>(off_J[(size_t)jslot[(size_t)i]]);
             S.Jb = c->at<uint32_t>(off_Jb[(size_t)jslot[(size_t)i]]);
+            S.Jt = c->at<uint32_t>(off_Jt[(size_t)jslot[(size_t)i]]);
             S.state = c->at<uint32_t>(off_state[ch]);
             S.H = c->at<int32_t>(off_H[ch]);
             S.snap = c->at<uint32_t>(off_snap[ch]);
@@ -1137,7 +1188,7 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     c->sk_lds = sk_lds_bytes(c->sk_max_n);
     hip_check(sk_init(c->sk_d, c->n_chains, 256, nullptr));
     hip_check(sk_recompute(c->sks_d, count, c->sk_d, c->sk_max_n, 0, c->err_d, nullptr));
-    hip_check(hipDeviceSynchronize());
+    hip_check(hipStreamSynchronize(nullptr));
 }
 
 template <class F>
@@ -1224,7 +1275,7 @@ sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream)
     return guarded([&]() {
         hip_check(hipSetDevice(c->device));
         hipStream_t s = (hipStream_t)stream;
-        c->last_stream = s;
+        c->note_stream(s);
         if (c->kind == 0) {
             const int64_t cap = std::max<int64_t>(
                 1, std::min<int64_t>(4096, ((int64_t)1 << 36) / std::max<int64_t>(1, c->updates_per_sweep)));
@@ -1261,6 +1312,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
     sg_status st = guarded([&]() {
         hip_check(hipSetDevice(c->device));
         hipStream_t s = (hipStream_t)stream;
+        c->note_stream(s);
         const int32_t kd = c->k_done();
         const int32_t K = c->K, R = c->R;
         out->count = c->count;
@@ -1352,8 +1404,7 @@ void sg_free(sg_ctx* c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
-    (void)hipDeviceSynchronize();
+    c->sync_own();
     c->release();
     delete c;
 }

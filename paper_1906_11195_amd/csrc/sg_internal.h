@@ -82,6 +82,7 @@ struct VbUnit {
 struct SkChain {
     const int8_t* J;           // [n][n]
     const uint32_t* Jb;        // [n][words_n] bit-packed rows, bit 1 = coupling -1
+    const uint32_t* Jt;        // [n_blocks][64][sk_tile_words()] the decider's tiles, contiguous
     uint32_t* state;           // [words_n] position-order bits (1 = spin -1)
     int32_t* H;                // [n] local fields between launches
     uint32_t* snap;            // [K][words_n]
@@ -140,6 +141,10 @@ hipError_t sk_sweep(const SkChain* chains, int n_chains, int threads, size_t lds
                     int32_t n_sweeps, int64_t t_max, int* err_flag, hipStream_t s);
 size_t sk_lds_bytes(int32_t n);
 int sk_threads();
+// Decider tiles: words per row of a 64-spin block (its own columns, then those
+// of the sk_window() blocks before it, two words each).
+int sk_tile_words();
+int sk_window();
 
 hipError_t vb_bond(const VbUnit* units, int n_units, int k_done, long long* bond_out,
                    const int32_t* unit_chain_ids, int k_cap, int threads, size_t lds_bytes,

@@ -184,13 +184,10 @@ hipError_t vb_bond(const VbUnit* units, int n_units, int k_done, long long* bond
                    hipStream_t s)
 {
     if (n_units <= 0 || k_done <= 0) return hipSuccess;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)vb_bond_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // set once (thread-safe initialisation of a local static)
+    static const hipError_t attr = hipFuncSetAttribute((const void*)vb_bond_kernel,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(vb_bond_kernel, dim3(n_units, k_done), dim3(threads), lds_bytes, s, units,
                        unit_chain_ids, k_cap, bond_out);
     return hipGetLastError();

@@ -42,6 +42,7 @@ namespace sg {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 // Pipeline depth (compile-time tuning parameters).
 #ifndef SG_SK_RING
@@ -52,10 +53,13 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 #endif
 constexpr int kRing = SG_SK_RING;   // blocks in flight between the roles
 constexpr int kWin = SG_SK_WIN;     // previous blocks the decider corrects for itself
-constexpr int kTileWords = 2 + 2 * kWin;   // per lane: own-block row, kWin previous rows
+constexpr int kTileWords = (2 + 2 * kWin + 3) & ~3;   // per lane: own-block row, kWin previous rows (16-byte multiple)
 constexpr int kThrCache = 512;      // threshold entries cached in LDS
 #ifndef SG_SK_UPD
 #define SG_SK_UPD 8
+#endif
+#ifndef SG_SK_SLEEP
+#define SG_SK_SLEEP 1   // s_sleep units (64 clocks) between polls of a wait
 #endif
 #ifndef SG_SK_UPB
 #define SG_SK_UPB 1
@@ -121,7 +125,7 @@ __device__ __forceinline__ void st_rel(int32_t* p, int32_t v)
 __device__ __forceinline__ bool wait_giveup(const SkLds& L, int& spins, int* err)
 {
     if (ld_acq(&L.sync[kAbort])) return true;
-    __builtin_amdgcn_s_sleep(1);
+    if (SG_SK_SLEEP > 0) __builtin_amdgcn_s_sleep(SG_SK_SLEEP);
     if (++spins > kSpinLimit) {
         st_rel(&L.sync[kAbort], 1);
         atomicOr(err, 2);
@@ -208,18 +212,21 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         // coupling tiles (bit-packed, bit 1 = J -1) of lane i's own row
         // 64 b + i: its columns in block b, then in blocks b - d, d = 1..DW
         // (J is symmetric, so bit j is the coupling of spin j of that block to
-        // spin i); the tiles of the next block are loaded while this block's
-        // uniforms are drawn
-        uint32_t tw[2 * (kWin + 1)];
+        // spin i), stored contiguously per block by the host (zero past the
+        // last row or column and beyond DW); the tiles of the next block are
+        // loaded while this block's uniforms are drawn
+        static_assert(kTileWords % 4 == 0, "tiles are read as 16-byte vectors");
+        uint32_t tw[kTileWords];
+        const SG_G v4u* __restrict__ Jt = (const SG_G v4u*)gl(ch->Jt);
         auto load_tiles = [&](int32_t bq) {
-            const int32_t rr = (bq << 6) + lane;
+            const SG_G v4u* src = Jt + ((size_t)((bq << 6) + lane) * kTileWords) / 4;
 #pragma unroll
-            for (int d = 0; d <= kWin; ++d) {
-                const bool live = d <= DW && rr < n;   // d <= DW < NB: one wrap at most
-                const int32_t bb = !live ? 0 : (bq - d < 0 ? bq - d + NB : bq - d);
-                const int32_t w0 = 2 * bb, w1 = 2 * bb + 1;
-                tw[2 * d] = live ? Jb[(int64_t)rr * wn + w0] : 0u;
-                tw[2 * d + 1] = (live && w1 < wn) ? Jb[(int64_t)rr * wn + w1] : 0u;
+            for (int v = 0; v < kTileWords / 4; ++v) {
+                const v4u q = src[v];
+                tw[4 * v] = q.x;
+                tw[4 * v + 1] = q.y;
+                tw[4 * v + 2] = q.z;
+                tw[4 * v + 3] = q.w;
             }
         };
         if (total > 0) load_tiles(0);
@@ -322,12 +329,12 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             }
             // Decisions in rounds.  A lane's decision is certain once it
             // cannot change whichever way the undecided lanes before it go:
-            // each of them moves its field by at most 2.  The first undecided
-            // lane is always certain, so every round decides at least one lane
-            // (the exact sequential result, usually in one or two rounds).  The
-            // flips decided in a round change the fields of the lanes after
-            // them at once; after the last round every lane adds the flips
-            // after it.
+            // each of them would move its x by 2, in a direction known from
+            // the spins and the coupling.  The first undecided lane is always
+            // certain, so every round decides at least one lane (the exact
+            // sequential result, in about three rounds).  The flips decided in
+            // a round change the fields of the lanes after them at once; after
+            // the last round every lane adds the flips after it.
             unsigned long long SB = __builtin_amdgcn_ballot_w64(sb != 0u);
             unsigned long long und = __builtin_amdgcn_ballot_w64(act);
             unsigned long long Fp = 0ull, Fn = 0ull;
@@ -337,9 +344,14 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                     (uint32_t)(und >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)und, 0u));
                 const bool mine = (und >> lane) & 1ull;
                 const int32_t x = sb ? -Hp : Hp;
-                const int32_t slack = 2 * (int32_t)below;
-                const unsigned long long F = __builtin_amdgcn_ballot_w64(mine && x + slack <= xm);
-                const unsigned long long K = __builtin_amdgcn_ballot_w64(mine && x - slack > xm);
+                // a flip of an undecided lane j before this one changes x by
+                // -2 s s_j J_j: down where s s_j J_j > 0 (spin and coupling
+                // bits XOR to 0), up elsewhere
+                const unsigned long long own = sb ? ~0ull : 0ull;
+                const int32_t dn = __popcll(~(SB ^ D ^ own) & und & lt);
+                const int32_t upc = (int32_t)below - dn;
+                const unsigned long long F = __builtin_amdgcn_ballot_w64(mine && x + 2 * upc <= xm);
+                const unsigned long long K = __builtin_amdgcn_ballot_w64(mine && x - 2 * dn > xm);
                 und &= ~(F | K);
                 const unsigned long long fp = F & SB, fn = F & ~SB;
                 Hp += delta(fp & lt, fn & lt, D);
@@ -696,6 +708,8 @@ size_t sk_lds_bytes(int32_t n)
 }
 
 int sk_threads() { return kSkThreads; }
+int sk_tile_words() { return kTileWords; }
+int sk_window() { return kWin; }
 
 hipError_t sk_init(const SkChain* chains, int n_chains, int threads, hipStream_t s)
 {
@@ -726,13 +740,10 @@ hipError_t sk_sweep(const SkChain* chains, int n_chains, int, size_t lds_bytes, 
                     int32_t n_sweeps, int64_t t_max, int* err_flag, hipStream_t s)
 {
     if (n_chains <= 0 || n_sweeps <= 0) return hipSuccess;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)sk_sweep_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // set once (thread-safe initialisation of a local static)
+    static const hipError_t attr = hipFuncSetAttribute((const void*)sk_sweep_kernel,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(sk_sweep_kernel, dim3(n_chains), dim3(kSkThreads), lds_bytes, s, chains, t0,
                        n_sweeps, t_max, err_flag);
     return hipGetLastError();

@@ -628,13 +628,10 @@ hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStr
 
 hipError_t vb_prepare()
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)vb_sweep_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // set once (thread-safe initialisation of a local static)
+    static const hipError_t attr = hipFuncSetAttribute((const void*)vb_sweep_kernel,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
     return hipSuccess;
 }
 

@@ -3,9 +3,9 @@
 Requests (VB or SK aging runs of different sizes, temperatures and lengths)
 arrive over time.  The server admits a request as soon as a slot is free and
 its device-memory footprint fits the budget, keeps its spins on the device,
-and advances every admitted run in chunks of sweeps on a pool of streams, so
-that the runs of many requests are in flight on the device at once and a new
-arrival does not wait for the others to finish.  A finished run is measured
+and enqueues every admitted run's sweeps at admission on one of a pool of
+streams, so that the runs of many requests are in flight on the device at
+once and a new arrival does not wait for the others to finish.  A finished run is measured
 (its observables copied to the host), its memory is released and the next
 waiting request can take its place.
 
@@ -113,11 +113,14 @@ class AgingServer:
     A free stream takes every request that has arrived with the same kind and
     run length as the oldest waiting one (up to `max_batch`, within the HBM
     budget) and runs them as one context: all their chains advance in the same
-    launches (large VB graphs split over several workgroups), and new
-    arrivals form the next batch on the next free stream while earlier ones
-    run.  A batch is measured and released when its runs are done; each
-    request's result is its own slice of the batch's observables, identical to
-    the run alone."""
+    launches (large VB graphs split over several workgroups).  A batch's
+    context is built on a worker thread (the host build releases the
+    interpreter lock), and the worker enqueues all of the batch's sweeps on
+    its stream (`chunk_sweeps` per call) at once, so the device never waits
+    for the loop; new arrivals form the next batch on the next free stream
+    while earlier ones run.  A batch is measured and released when its stream
+    has finished; each request's result is its own slice of the batch's
+    observables, identical to the run alone."""
 
     def __init__(self, hbm_budget: int = 32 << 30, max_active: int = 64, chunk_sweeps: int = 256,
                  n_streams: int = 4, flags: int = MEASURE_OBS | MEASURE_SPINS, max_batch: int = 64):
@@ -126,7 +129,7 @@ class AgingServer:
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.max_batch = int(max_batch)
-        self.chunk = int(chunk_sweeps)
+        self.chunk = max(1, int(chunk_sweeps))
         self.flags = flags
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
 
@@ -134,47 +137,66 @@ class AgingServer:
         return select_batch(pending, now, time_scale, used, active_requests, self.budget, self.max_batch,
                             self.max_active)
 
+    def _start(self, batch, stream):
+        """Worker: builds the batch's context and enqueues all its sweeps on
+        `stream`; returns (context, completion event)."""
+        torch = self.torch
+        with torch.cuda.stream(stream):
+            descs = [descriptor(r) for r in batch]
+            make = sg_create_vb if batch[0].kind == "vb" else sg_create_sk
+            ctx = make(descs, t_max=batch[0].sweeps)
+            try:
+                done, length = 0, batch[0].sweeps
+                while done < length:
+                    k = min(self.chunk, length - done)
+                    sg_sweep(ctx, k, stream=stream)
+                    done += k
+                ev = torch.cuda.Event()
+                ev.record(stream)
+            except BaseException:
+                sg_free(ctx)
+                raise
+        return ctx, ev
+
     def run(self, requests, time_scale: float = 1.0, max_wall: Optional[float] = None) -> List[Result]:
         """Serves `requests` (arrival times in seconds from the start, scaled by
         time_scale).  Returns one Result per finished request."""
-        torch = self.torch
+        from concurrent.futures import ThreadPoolExecutor
         pending = sorted(requests, key=lambda r: r.arrival)
         free = list(range(len(self.streams)))
         batches = []
         used = 0
         results: List[Result] = []
+        pool = ThreadPoolExecutor(max_workers=len(self.streams))
         t0 = time.perf_counter()
-        while pending or batches:
-            now = time.perf_counter() - t0
-            if max_wall is not None and now > max_wall:
-                break
-            progressed = False
-            # admission: a free stream takes the next batch
-            while free and pending:
-                n_active = sum(len(b["reqs"]) for b in batches)
-                batch, fp = self._take_batch(pending, now, time_scale, used, n_active)
-                if not batch:
+        try:
+            while pending or batches:
+                now = time.perf_counter() - t0
+                if max_wall is not None and now > max_wall:
                     break
-                ids = set(id(r) for r in batch)
-                pending = [r for r in pending if id(r) not in ids]
-                si = free.pop(0)
-                stream = self.streams[si]
-                with torch.cuda.stream(stream):
-                    descs = [descriptor(r) for r in batch]
-                    make = sg_create_vb if batch[0].kind == "vb" else sg_create_sk
-                    ctx = make(descs, t_max=batch[0].sweeps)
-                batches.append(dict(reqs=batch, ctx=ctx, si=si, stream=stream, done=0, event=None, fp=fp,
-                                    admitted=time.perf_counter() - t0))
-                used += fp
-                progressed = True
-            for b in list(batches):
-                ev = b["event"]
-                if ev is not None and not ev.query():
-                    continue
-                length = b["reqs"][0].sweeps
-                if b["done"] >= length:
-                    obs = sg_measure(b["ctx"], self.flags, stream=b["stream"])
-                    sg_free(b["ctx"])
+                progressed = False
+                # admission: a free stream takes the next batch
+                while free and pending:
+                    n_active = sum(len(b["reqs"]) for b in batches)
+                    batch, fp = self._take_batch(pending, now, time_scale, used, n_active)
+                    if not batch:
+                        break
+                    ids = set(id(r) for r in batch)
+                    pending = [r for r in pending if id(r) not in ids]
+                    si = free.pop(0)
+                    fut = pool.submit(self._start, batch, self.streams[si])
+                    batches.append(dict(reqs=batch, fut=fut, si=si, fp=fp, admitted=now))
+                    used += fp
+                    progressed = True
+                # completion: built, and its stream has run every sweep
+                for b in list(batches):
+                    if not b["fut"].done():
+                        continue
+                    ctx, ev = b["fut"].result()
+                    if not ev.query():
+                        continue
+                    obs = sg_measure(ctx, self.flags, stream=self.streams[b["si"]])
+                    sg_free(ctx)
                     fin = time.perf_counter() - t0
                     for i, req in enumerate(b["reqs"]):
                         results.append(Result(req.rid, req.kind, req.n, req.sweeps, req.arrival * time_scale,
@@ -183,24 +205,23 @@ class AgingServer:
                     free.append(b["si"])
                     batches.remove(b)
                     progressed = True
+                if not progressed:
+                    if batches:
+                        time.sleep(0.0002)
+                    elif pending:
+                        wait = pending[0].arrival * time_scale - (time.perf_counter() - t0)
+                        if wait > 0:
+                            time.sleep(min(wait, 0.01))
+        finally:
+            # release what is still in flight (after a time limit or an error)
+            for b in batches:
+                try:
+                    ctx, ev = b["fut"].result()
+                except BaseException:
                     continue
-                k = min(self.chunk, length - b["done"])
-                sg_sweep(b["ctx"], k, stream=b["stream"])
-                b["done"] += k
-                ev = torch.cuda.Event()
-                ev.record(b["stream"])
-                b["event"] = ev
-                progressed = True
-            if not progressed:
-                if batches:
-                    time.sleep(0.0002)
-                elif pending:
-                    wait = pending[0].arrival * time_scale - (time.perf_counter() - t0)
-                    if wait > 0:
-                        time.sleep(min(wait, 0.01))
-        for b in batches:
-            torch.cuda.synchronize()
-            sg_free(b["ctx"])
+                ev.synchronize()
+                sg_free(ctx)
+            pool.shutdown(wait=True)
         return results
 
 
