@@ -212,7 +212,9 @@ typedef struct sg_obs {
 
 /* Creates a context holding `count` VB instances on the current HIP device,
  * builds their graphs (SG_START_RANDOM chains are initialised on the device)
- * and records the t = 0 snapshot.  Synchronous. */
+ * and records the t = 0 snapshot.  Synchronous: returns once its own set-up
+ * work (on the null stream) is done; work of other contexts keeps running.
+ * Different contexts may be created from different host threads at once. */
 sg_status sg_create_vb(const sg_vb_desc* d, int32_t count, const sg_opts* o, sg_ctx** out);
 
 /* Same for `count` SK instances. */
@@ -230,7 +232,8 @@ sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream);
  * if an SK field check has failed since the context was created. */
 sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream);
 
-/* Waits for the context's last stream and releases everything it owns.
+/* Waits for every stream the context's calls have used (and for its set-up
+ * work), never for other contexts, and releases everything it owns.
  * sg_free(NULL) does nothing. */
 void sg_free(sg_ctx* c);
 

@@ -465,6 +465,9 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
     // pipeline: E = chunk to update next (rows + entries), R = the one after
     // (rows only)
     Stage E, R;
+    R.q = 0;
+    R.r0 = 0;
+    R.r1 = 0;
     Cursor cR{0, 0, wave - W};
     bool haveR = nsw > 0 && cursor_next(cR, W, wave, ncls, cls, nsw);
     if (haveR) {
@@ -485,12 +488,15 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
             const int32_t lo = cls_at(cls, k), hi = cls_at(cls, k + 1);
             const int32_t nck = n_chunks(cls, k);
             for (int32_t j = wave; j < nck; j += W) {
+                // the stage moves on unconditionally (past the last chunk of
+                // the launch it re-reads valid entries that are not used), so
+                // that the registers rotate without branches
                 const Stage cur = E;
+                E.q = R.q;
+                E.r0 = R.r0;
+                E.r1 = R.r1;
+                load_ents(ent, E);
                 if (haveR) {
-                    E.q = R.q;
-                    E.r0 = R.r0;
-                    E.r1 = R.r1;
-                    load_ents(ent, E);
                     haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
                     if (haveR) load_rows(row, cls, cR, lane, R);
                 }
