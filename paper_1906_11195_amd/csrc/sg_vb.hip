@@ -105,9 +105,12 @@ __device__ __forceinline__ int32_t cls_at(const int32_t* cls, int32_t k)
 }
 
 // Chunk cursor of one wavefront: sweep s, colour class k, chunk j of the class
-// (the aligned block (cls[k] >> 6) + j of 64 positions).
+// (the aligned block (cls[k] >> 6) + j of 64 positions).  The class's bounds
+// and chunk count are kept with it, so that a step inside a class reads
+// nothing from LDS.
 struct Cursor {
     int32_t s, k, j;
+    int32_t lo, hi, nck;
 };
 
 template <class PC>
@@ -117,18 +120,37 @@ __device__ __forceinline__ int32_t n_chunks(PC cls, int32_t k)
     return hi > lo ? ((hi - 1) >> 6) - (lo >> 6) + 1 : 0;
 }
 
+template <class PC>
+__device__ __forceinline__ void cursor_class(Cursor& c, PC cls)
+{
+    c.lo = cls_at(cls, c.k);
+    c.hi = cls_at(cls, c.k + 1);
+    c.nck = c.hi > c.lo ? ((c.hi - 1) >> 6) - (c.lo >> 6) + 1 : 0;
+}
+
+// A cursor before the first chunk of wavefront `wave` (cursor_next moves it
+// there).
+template <class PC>
+__device__ __forceinline__ Cursor cursor_start(int W, int wave, PC cls)
+{
+    Cursor c{0, 0, wave - W, 0, 0, 0};
+    cursor_class(c, cls);
+    return c;
+}
+
 // Moves to the next chunk owned by wavefront `wave`; false past the launch.
 template <class PC>
 __device__ __forceinline__ bool cursor_next(Cursor& c, int W, int wave, int32_t ncls, PC cls, int32_t nsw)
 {
     c.j += W;
     for (;;) {
-        if (c.j < n_chunks(cls, c.k)) return true;
+        if (c.j < c.nck) return true;
         c.j = wave;
         if (++c.k == ncls) {
             c.k = 0;
             if (++c.s >= nsw) return false;
         }
+        cursor_class(c, cls);
     }
 }
 
@@ -141,9 +163,8 @@ struct Stage {
 template <class PR, class PC>
 __device__ __forceinline__ void load_rows(PR row, PC cls, const Cursor& c, int lane, Stage& st)
 {
-    const int32_t lo = cls_at(cls, c.k), hi = cls_at(cls, c.k + 1);
-    st.q = (((lo >> 6) + c.j) << 6) + lane;
-    const bool act = st.q >= lo && st.q < hi;
+    st.q = (((c.lo >> 6) + c.j) << 6) + lane;
+    const bool act = st.q >= c.lo && st.q < c.hi;
     st.r0 = act ? row[st.q] : 0;
     st.r1 = act ? row[st.q + 1] : 0;
 }
@@ -342,7 +363,7 @@ __device__ __forceinline__ void vb_fill(const VbLds& L, Cursor& pc, bool& pc_ok,
     for (int32_t i = 0; i < B; ++i) {
         uint32_t base = 0u, tt = 0u;
         if (pc_ok) {
-            base = (uint32_t)((((cls_at(cls, pc.k) >> 6) + pc.j) << 6));
+            base = (uint32_t)((((pc.lo >> 6) + pc.j) << 6));
             tt = (uint32_t)(t0 + pc.s);
             pc_ok = cursor_next(pc, W, wave, ncls, cls, nsw);
         }
@@ -362,6 +383,20 @@ __device__ __forceinline__ void vb_fill(const VbLds& L, Cursor& pc, bool& pc_ok,
                                    L.ri[2 * c + 1]);
         L.xch[wl * 64 + lane] = make_uint4(A.x, A.y, A.z, A.w);
     }
+    wave_sync();
+}
+
+// One pass for the chunk at positions base.. of sweep t (the only chunk of a
+// batch when 8 / nch < 2, i.e. for 5 to 8 chains): no cursor, no table.
+__device__ __forceinline__ void vb_fill_one(const VbLds& L, uint32_t base, uint32_t t, int wl, int lane,
+                                            int32_t nch, uint64_t key)
+{
+    const uint32_t mul = (65536u + (uint32_t)nch - 1u) / (uint32_t)nch;
+    const uint32_t m = (uint32_t)lane;
+    const uint32_t dq = (m * mul) >> 16;           // m / nch = group (lanes past 8 nch draw unused blocks)
+    const uint32_t c = m - dq * (uint32_t)nch;
+    const U4 A = philox_stream(key, (base >> 3) + (dq & 7u), t, kDomSweepHi, L.ri[2 * c], L.ri[2 * c + 1]);
+    L.xch[wl * 64 + lane] = make_uint4(A.x, A.y, A.z, A.w);
     wave_sync();
 }
 
@@ -456,8 +491,10 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
     // Philox batches: cursor of the next chunk to draw for, chunks left in
     // the current batch and the batch position of the next chunk
     const int32_t B = vb_batch_chunks(nch);
-    Cursor pc{0, 0, wave - W};
-    bool pc_ok = nsw > 0 && cursor_next(pc, W, wave, ncls, cls, nsw);
+    // (with 8 chain slots a batch is one chunk: its blocks are drawn for the
+    // chunk itself, and the cursor is not needed)
+    Cursor pc = cursor_start(W, wave, cls);
+    bool pc_ok = RPAD != 8 && nsw > 0 && cursor_next(pc, W, wave, ncls, cls, nsw);
     int32_t left = 0, bi = 0;
     const uint32_t* xg = (const uint32_t*)(L.xch + wl * 64);
     const uint32_t lane_off = (uint32_t)(lane >> 3) * (uint32_t)nch * 4u + (((uint32_t)lane & 7u) >> 1);
@@ -468,7 +505,7 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
     R.q = 0;
     R.r0 = 0;
     R.r1 = 0;
-    Cursor cR{0, 0, wave - W};
+    Cursor cR = cursor_start(W, wave, cls);
     bool haveR = nsw > 0 && cursor_next(cR, W, wave, ncls, cls, nsw);
     if (haveR) {
         load_rows(row, cls, cR, lane, E);
@@ -500,7 +537,11 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
                     haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
                     if (haveR) load_rows(row, cls, cR, lane, R);
                 }
-                if (left == 0) {
+                if (RPAD == 8) {
+                    vb_fill_one(L, (uint32_t)(((lo >> 6) + j) << 6), t, wl, lane, nch, key);
+                    left = 1;
+                    bi = 0;
+                } else if (left == 0) {
                     vb_fill(L, pc, pc_ok, cls, ncls, nsw, W, wave, wl, lane, t0, nch, key);
                     left = B;
                     bi = 0;
