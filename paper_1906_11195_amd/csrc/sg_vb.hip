@@ -388,14 +388,25 @@ __device__ __forceinline__ void vb_fill(const VbLds& L, Cursor& pc, bool& pc_ok,
 
 // One pass for the chunk at positions base.. of sweep t (the only chunk of a
 // batch when 8 / nch < 2, i.e. for 5 to 8 chains): no cursor, no table.
-__device__ __forceinline__ void vb_fill_one(const VbLds& L, uint32_t base, uint32_t t, int wl, int lane,
-                                            int32_t nch, uint64_t key)
+// Lane m draws group g of chain c, m = g nch + c (lanes past 8 nch draw
+// blocks nobody reads); `fr` holds (g, replica, instance), fixed per lane.
+struct FillLane {
+    uint32_t g, rep, inst;
+};
+
+__device__ __forceinline__ FillLane fill_lane(const VbLds& L, int lane, int32_t nch)
 {
     const uint32_t mul = (65536u + (uint32_t)nch - 1u) / (uint32_t)nch;
     const uint32_t m = (uint32_t)lane;
-    const uint32_t dq = (m * mul) >> 16;           // m / nch = group (lanes past 8 nch draw unused blocks)
+    const uint32_t dq = (m * mul) >> 16;           // m / nch
     const uint32_t c = m - dq * (uint32_t)nch;
-    const U4 A = philox_stream(key, (base >> 3) + (dq & 7u), t, kDomSweepHi, L.ri[2 * c], L.ri[2 * c + 1]);
+    return FillLane{dq & 7u, L.ri[2 * c], L.ri[2 * c + 1]};
+}
+
+__device__ __forceinline__ void vb_fill_one(const VbLds& L, const FillLane& fr, uint32_t base, uint32_t t, int wl,
+                                            int lane, uint64_t key)
+{
+    const U4 A = philox_stream(key, (base >> 3) + fr.g, t, kDomSweepHi, fr.rep, fr.inst);
     L.xch[wl * 64 + lane] = make_uint4(A.x, A.y, A.z, A.w);
     wave_sync();
 }
@@ -515,6 +526,7 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
     }
     __syncthreads();
 
+    const FillLane fr = fill_lane(L, lane, nch);
     uint32_t acc[RPAD];   // wave-uniform; flushed to LDS once per sweep
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) acc[c] = 0;
@@ -538,7 +550,7 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
                     if (haveR) load_rows(row, cls, cR, lane, R);
                 }
                 if (RPAD == 8) {
-                    vb_fill_one(L, (uint32_t)(((lo >> 6) + j) << 6), t, wl, lane, nch, key);
+                    vb_fill_one(L, fr, (uint32_t)(((lo >> 6) + j) << 6), t, wl, lane, key);
                     left = 1;
                     bi = 0;
                 } else if (left == 0) {
