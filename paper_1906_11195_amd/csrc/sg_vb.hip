@@ -70,7 +70,6 @@ struct VbLds {
     int32_t* flag;                // [4]: split units' abort flag
     int32_t* cls;                 // [kMaxCls + 1] first position of each colour class
     uint32_t* ri;                 // [8][2]: replica, instance of each chain
-    uint32_t* ctab;               // [waves][8][2]: first position and sweep of a batch's chunks
     uint4* xch;                   // [waves][64] Philox blocks of a batch of chunks
     int32_t* area;                // resident adjacency: row starts, then entries
 };
@@ -90,8 +89,7 @@ __device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr, 
     L.flag = (int32_t*)(L.accs + kVbMaxChains);
     L.cls = L.flag + 4;
     L.ri = (uint32_t*)(L.cls + kMaxCls + 4);
-    L.ctab = L.ri + 2 * kVbMaxChains;
-    L.xch = (uint4*)(L.ctab + (nthr >> 6) * 2 * kVbMaxChains);
+    L.xch = (uint4*)(L.ri + 2 * kVbMaxChains);
     L.area = (int32_t*)(L.xch + (nthr >> 6) * 64);
     return L;
 }
@@ -353,34 +351,37 @@ __device__ bool vb_exchange(const VbUnit* __restrict__ up, const VbLds& L, int32
 // max(1, 8 / nch) of them, following cursor pc) into its LDS batch: block
 // m = i 8 nch + g nch + c is group g of chunk i for chain c (lanes past the
 // last such block draw nothing that is used).
-template <class PC>
+template <int B, class PC>
 __device__ __forceinline__ void vb_fill(const VbLds& L, Cursor& pc, bool& pc_ok, PC cls, int32_t ncls,
                                         int32_t nsw, int W, int wave, int wl, int lane, int64_t t0,
                                         int32_t nch, uint64_t key)
 {
-    const int32_t B = vb_batch_chunks(nch);
-    uint32_t* ct = L.ctab + wl * 2 * kVbMaxChains;
-    for (int32_t i = 0; i < B; ++i) {
-        uint32_t base = 0u, tt = 0u;
+    // the batch's chunk positions and sweeps stay in scalar registers; each
+    // lane picks its chunk's pair by selection (no table in LDS)
+    uint32_t base[B], tt[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        base[i] = 0u;
+        tt[i] = 0u;
         if (pc_ok) {
-            base = (uint32_t)((((pc.lo >> 6) + pc.j) << 6));
-            tt = (uint32_t)(t0 + pc.s);
+            base[i] = (uint32_t)((((pc.lo >> 6) + pc.j) << 6));
+            tt[i] = (uint32_t)(t0 + pc.s);
             pc_ok = cursor_next(pc, W, wave, ncls, cls, nsw);
         }
-        if (lane == 0) {
-            ct[2 * i] = base;
-            ct[2 * i + 1] = tt;
-        }
     }
-    wave_sync();
     const uint32_t mul = (65536u + (uint32_t)nch - 1u) / (uint32_t)nch;
     {
         const uint32_t m = (uint32_t)lane;
         const uint32_t dq = (m * mul) >> 16;           // m / nch = 8 i + g
         const uint32_t c = m - dq * (uint32_t)nch;
         const uint32_t i = min(dq >> 3, (uint32_t)(B - 1)), g = dq & 7u;
-        const U4 A = philox_stream(key, (ct[2 * i] >> 3) + g, ct[2 * i + 1], kDomSweepHi, L.ri[2 * c],
-                                   L.ri[2 * c + 1]);
+        uint32_t bq = base[0], tq = tt[0];
+#pragma unroll
+        for (int k = 1; k < B; ++k) {
+            bq = i == (uint32_t)k ? base[k] : bq;
+            tq = i == (uint32_t)k ? tt[k] : tq;
+        }
+        const U4 A = philox_stream(key, (bq >> 3) + g, tq, kDomSweepHi, L.ri[2 * c], L.ri[2 * c + 1]);
         L.xch[wl * 64 + lane] = make_uint4(A.x, A.y, A.z, A.w);
     }
     wave_sync();
@@ -554,7 +555,7 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
                     left = 1;
                     bi = 0;
                 } else if (left == 0) {
-                    vb_fill(L, pc, pc_ok, cls, ncls, nsw, W, wave, wl, lane, t0, nch, key);
+                    vb_fill<(RPAD < 8 ? 8 / RPAD : 1)>(L, pc, pc_ok, cls, ncls, nsw, W, wave, wl, lane, t0, nch, key);
                     left = B;
                     bi = 0;
                 }
@@ -675,7 +676,7 @@ size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads)
     const size_t sw = (size_t)VbLayout(rpad).words(n);
     const size_t waves = (size_t)threads / 64;
     return ((sw + 3) & ~(size_t)3) * 4 + (size_t)kVbMaxChains * kTab * 4 + kVbMaxChains * 8 + 16 +
-           (kMaxCls + 4) * 4 + kVbMaxChains * 8 + waves * kVbMaxChains * 8 + waves * 64 * 16;
+           (kMaxCls + 4) * 4 + kVbMaxChains * 8 + waves * 64 * 16;
 }
 
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStream_t s)
