@@ -189,17 +189,23 @@ __device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, con
     using S = Sl<RPAD>;
     const int lane = threadIdx.x & 63;
     const uint32_t hsel = (uint32_t)lane & 7u;
-    const uint32_t width = RPAD == 8 ? (wide ? 8u : 4u) : (uint32_t)S::P;
+    // RPAD 8: the 4-bit fields (chain c at bit 4c of cA) are spread to the
+    // 8-bit layout (even chains in cA, odd chains in cB, chain c at byte
+    // c / 2), so every count is extracted at a constant position and width
+    if (RPAD == 8 && !wide) {
+        cB = (cA >> 4) & 0x0F0F0F0Fu;
+        cA &= 0x0F0F0F0Fu;
+    }
+    constexpr uint32_t width = RPAD == 8 ? 8u : (uint32_t)S::P;
     auto count = [&](int c) -> uint32_t {
         if (RPAD == 1) return cA;
-        const uint32_t fsh = RPAD == 8 ? (wide ? 8u * (uint32_t)(c >> 1) : 4u * (uint32_t)c) : (uint32_t)(c * S::P);
+        const uint32_t fsh = RPAD == 8 ? 8u * (uint32_t)(c >> 1) : (uint32_t)(c * S::P);
         return __builtin_amdgcn_ubfe(RPAD == 8 && (c & 1) ? cB : cA, fsh, width);
     };
     // The table holds chain c's entry for x at word c kTab + 64 - x, so the
-    // entry for x = deg - 2 cnt is at byte 4 (64 - deg) + 8 cnt.
-    uint32_t tbase = (uint32_t)(64 - deg) * 4u;
-    asm volatile("" : "+v"(tbase));   // one register: each address is then a single shift-add
-    const char* tb = (const char*)L.thr;
+    // entry for x = deg - 2 cnt is at byte 4 (64 - deg) + 8 cnt; `tb` includes
+    // the lane's 4 (64 - deg), so each address is a single shift-add
+    const char* tb = (const char*)L.thr + (uint32_t)(64 - deg) * 4u;
     const uint32_t hs = 16u * (hsel & 1u);
     const unsigned long long am = __builtin_amdgcn_ballot_w64(act);
     uint32_t fl = 0;
@@ -207,7 +213,7 @@ __device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, con
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) {
         if (c < nch) {
-            const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (count(c) << 3) + tbase);
+            const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (count(c) << 3));
             const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
             const bool f = rh < th;
             const unsigned long long m = __builtin_amdgcn_ballot_w64(f) & am;
@@ -223,7 +229,7 @@ __device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, con
         for (int c = 0; c < RPAD; ++c) {
             if (c < nch) {
                 const uint32_t cnt = count(c);
-                const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (cnt << 3) + tbase);
+                const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (cnt << 3));
                 const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
                 const bool ti = act && rh == th;
                 if (__builtin_amdgcn_ballot_w64(ti) != 0ull) {
@@ -287,7 +293,6 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
         }
     }
 
-    if (RPAD == 8 && !wide) cB = cA;
     const uint32_t fl = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key, acc);
     // write the flips back: every lane XORs its flips into its spin word (the
     // P lanes of a word are in this wavefront's chunk, nothing else writes it)
