@@ -254,28 +254,6 @@ void check_sk_desc(const sg_sk_desc& d)
     }
 }
 
-void sk_generate(int64_t n, uint64_t seed, uint32_t graph_id, int8_t* J)
-{
-    for (int64_t i = 0; i < n; ++i) J[i * n + i] = 0;
-    // one Philox block covers 128 consecutive idx = i N + j
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t j = i + 1;
-        while (j < n) {
-            const uint64_t idx = (uint64_t)i * (uint64_t)n + (uint64_t)j;
-            const uint64_t blk = idx >> 7;
-            const U4 w = philox_stream(seed, (uint32_t)blk, (uint32_t)(idx >> 39), kDomCoupling, 0u,
-                                       graph_id);
-            const uint64_t blk_end = (blk + 1) << 7;
-            for (; j < n && (uint64_t)i * (uint64_t)n + (uint64_t)j < blk_end; ++j) {
-                const uint64_t id2 = (uint64_t)i * (uint64_t)n + (uint64_t)j;
-                const uint32_t bit = (word_of(w, (uint32_t)((id2 >> 5) & 3u)) >> (id2 & 31u)) & 1u;
-                const int8_t v = bit ? (int8_t)-1 : (int8_t)1;
-                J[i * n + j] = v;
-                J[j * n + i] = v;
-            }
-        }
-    }
-}
 
 template <class F>
 void parallel_for(size_t count, F&& f)
@@ -305,6 +283,48 @@ void parallel_for(size_t count, F&& f)
         });
     for (auto& x : th) x.join();
     if (err.load() != 0) fail(err.load());
+}
+
+// Runs f(0..count-1) on several host threads when `par`, else in order.
+template <class F>
+void maybe_parallel(bool par, size_t count, F&& f)
+{
+    if (par) {
+        parallel_for(count, f);
+    } else {
+        for (size_t i = 0; i < count; ++i) f(i);
+    }
+}
+
+// SK couplings: the upper triangle row by row (one Philox block covers 128
+// consecutive idx = i N + j), then the lower triangle mirrored tile by tile;
+// both passes on several host threads when `par`.
+void sk_generate(int64_t n, uint64_t seed, uint32_t graph_id, int8_t* J, bool par)
+{
+    maybe_parallel(par, (size_t)n, [&](size_t ii) {
+        const int64_t i = (int64_t)ii;
+        J[i * n + i] = 0;
+        int64_t j = i + 1;
+        while (j < n) {
+            const uint64_t idx = (uint64_t)i * (uint64_t)n + (uint64_t)j;
+            const uint64_t blk = idx >> 7;
+            const U4 w = philox_stream(seed, (uint32_t)blk, (uint32_t)(idx >> 39), kDomCoupling, 0u,
+                                       graph_id);
+            const uint64_t blk_end = (blk + 1) << 7;
+            for (; j < n && (uint64_t)i * (uint64_t)n + (uint64_t)j < blk_end; ++j) {
+                const uint64_t id2 = (uint64_t)i * (uint64_t)n + (uint64_t)j;
+                const uint32_t bit = (word_of(w, (uint32_t)((id2 >> 5) & 3u)) >> (id2 & 31u)) & 1u;
+                J[i * n + j] = bit ? (int8_t)-1 : (int8_t)1;
+            }
+        }
+    });
+    const int64_t nt = (n + 63) / 64;
+    maybe_parallel(par, (size_t)nt, [&](size_t bi) {
+        const int64_t r0 = (int64_t)bi * 64, r1 = std::min(n, r0 + 64);
+        for (int64_t c0 = 0; c0 < r1; c0 += 64)
+            for (int64_t i = r0; i < r1; ++i)
+                for (int64_t k = c0; k < std::min(i, c0 + 64); ++k) J[i * n + k] = J[k * n + i];
+    });
 }
 
 int32_t grid_size(int64_t t_max)
@@ -1081,21 +1101,26 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     // couplings: generated on the host in parallel, or copied; int8 rows for
     // the MFMA contractions and bit-packed rows (bit 1 = -1, 8x fewer bytes)
     // for the field updates of the sweep
-    parallel_for(jrep.size(), [&](size_t j) {
+    // (a few samples: each one's passes run on several threads; many: the
+    // samples do)
+    const bool inner = jrep.size() < 4;
+    maybe_parallel(!inner, jrep.size(), [&](size_t j) {
         const sg_sk_desc& r = d[jrep[j]];
         const int64_t n = r.n, wn = (n + 31) / 32;
         std::vector<int8_t> J;
         const int8_t* src = r.J;
         if (!src) {
             J.resize((size_t)(n * n));
-            sk_generate(n, r.seed, r.graph_id, J.data());
+            sk_generate(n, r.seed, r.graph_id, J.data(), inner);
             src = J.data();
         }
         hip_check(hipMemcpy(c->at<void>(off_J[j]), src, (size_t)(n * n), hipMemcpyHostToDevice));
         std::vector<uint32_t> Jb((size_t)(n * wn), 0u);
-        for (int64_t i = 0; i < n; ++i)
+        maybe_parallel(inner, (size_t)n, [&](size_t ii) {
+            const int64_t i = (int64_t)ii;
             for (int64_t k = 0; k < n; ++k)
                 if (src[i * n + k] < 0) Jb[(size_t)(i * wn + (k >> 5))] |= 1u << (k & 31);
+        });
         hip_check(hipMemcpy(c->at<void>(off_Jb[j]), Jb.data(), Jb.size() * 4, hipMemcpyHostToDevice));
         // the decider's tiles: row 64 b + l, words 2 bb and 2 bb + 1 for
         // bb = b - d (cyclic), d = 0..DW with DW = min(window, blocks - 1)
@@ -1443,7 +1468,7 @@ sg_status sg_sk_inspect(const sg_sk_desc* d, int8_t* J, uint64_t* thr)
         const int64_t n = d->n;
         if (J) {
             if (d->J) std::memcpy(J, d->J, (size_t)(n * n));
-            else sk_generate(n, d->seed, d->graph_id, J);
+            else sk_generate(n, d->seed, d->graph_id, J, true);
         }
         if (thr) {
             const double s = 1.0 / std::sqrt((double)n);
