@@ -444,9 +444,15 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
 // (each variant is a function of its own so that its registers are
 // allocated for it alone)
 template <int RPAD, bool RES, bool SPLIT>
-__device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, uint32_t* smem, int64_t t0, int32_t nsw,
-                       int64_t t_max)
+__device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, uint32_t* smem_arr, uint32_t lds0,
+                                                int64_t t0, int32_t nsw, int64_t t_max)
 {
+    // With fewer than 8 chain slots the dynamic LDS base is taken as a plain
+    // offset: from the array itself this (called) function re-reads the base
+    // from a per-kernel table at each use, and each re-read waits for all
+    // outstanding LDS operations.  (With 8 slots the register the offset
+    // would hold costs more than the re-reads: measured.)
+    uint32_t* smem = RPAD == 8 ? smem_arr : (uint32_t*)(__attribute__((address_space(3))) uint32_t*)(size_t)lds0;
     const int tid = threadIdx.x, nthr = blockDim.x;
     // wave index made explicitly wave-uniform: the chunk cursor then lives in
     // scalar registers and class bounds come from scalar loads; a member of a
@@ -600,28 +606,30 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
                                                         int32_t nsw, int64_t t_max)
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+    uint32_t lds0 = (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t*)smem;
+    asm volatile("" : "+s"(lds0));   // an opaque value: the callee cannot re-derive it from the array
     const VbUnit* up = (const VbUnit*)(gl(units) + blockIdx.x);
     const int64_t t0 = *gl(t0p);
     if (up->resident) {
         switch (up->rpad) {
-            case 1: vb_run<1, true, false>(up, smem, t0, nsw, t_max); break;
-            case 2: vb_run<2, true, false>(up, smem, t0, nsw, t_max); break;
-            case 4: vb_run<4, true, false>(up, smem, t0, nsw, t_max); break;
-            default: vb_run<8, true, false>(up, smem, t0, nsw, t_max); break;
+            case 1: vb_run<1, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 2: vb_run<2, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 4: vb_run<4, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+            default: vb_run<8, true, false>(up, smem, lds0, t0, nsw, t_max); break;
         }
     } else if (up->members > 1) {
         switch (up->rpad) {
-            case 1: vb_run<1, false, true>(up, smem, t0, nsw, t_max); break;
-            case 2: vb_run<2, false, true>(up, smem, t0, nsw, t_max); break;
-            case 4: vb_run<4, false, true>(up, smem, t0, nsw, t_max); break;
-            default: vb_run<8, false, true>(up, smem, t0, nsw, t_max); break;
+            case 1: vb_run<1, false, true>(up, smem, lds0, t0, nsw, t_max); break;
+            case 2: vb_run<2, false, true>(up, smem, lds0, t0, nsw, t_max); break;
+            case 4: vb_run<4, false, true>(up, smem, lds0, t0, nsw, t_max); break;
+            default: vb_run<8, false, true>(up, smem, lds0, t0, nsw, t_max); break;
         }
     } else {
         switch (up->rpad) {
-            case 1: vb_run<1, false, false>(up, smem, t0, nsw, t_max); break;
-            case 2: vb_run<2, false, false>(up, smem, t0, nsw, t_max); break;
-            case 4: vb_run<4, false, false>(up, smem, t0, nsw, t_max); break;
-            default: vb_run<8, false, false>(up, smem, t0, nsw, t_max); break;
+            case 1: vb_run<1, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 2: vb_run<2, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 4: vb_run<4, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            default: vb_run<8, false, false>(up, smem, lds0, t0, nsw, t_max); break;
         }
     }
 }
