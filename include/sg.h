@@ -81,7 +81,7 @@ typedef int32_t sg_status;
 #define SG_EDEVICE (-3)  /* HIP runtime error or no usable gfx950 device */
 #define SG_ESTATE (-4)   /* call not valid in the context's state */
 #define SG_EPARITY (-5)  /* SK incremental fields disagreed with the exact recompute */
-#define SG_ENOTSUP (-6)  /* valid request outside this build's limits */
+#define SG_ENOTSUP (-6)  /* valid request outside the library's limits */
 
 #define SG_START_RANDOM 0   /* Philox random start (the paper's quench) */
 #define SG_START_ALIGNED 1  /* all spins +1 (the SI's SK protocol) */
