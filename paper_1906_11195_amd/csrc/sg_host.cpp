@@ -785,6 +785,12 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     // least two 64-position chunks per wavefront of the largest class, and
     // the members of all split units of a context use at most a quarter of
     // the CUs, so that they can all be resident at once next to other work.
+    // The barriers' device-scope fences slow every workgroup that shares the
+    // members' caches, so the automatic choice splits at most two units, and
+    // only units with at least three times the work of the largest unit left
+    // whole: then they alone set the launch's duration (measured with 65536
+    // spins and 6 chains per graph: 1 or 2 graphs, 106 -> 53 or 66 us per
+    // sweep; 8 to 128 equal graphs, 106 -> 136 to 225 us when split).
     // opts.split_members: 0 automatic, 1 never, k >= 2 every unit that has
     // the chunks for k members (tests, tuning).  No effect on any result.
     {
@@ -799,9 +805,18 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         for (size_t i = 0; i < plan.size(); ++i) by_work[i] = i;
         std::stable_sort(by_work.begin(), by_work.end(),
                          [&](size_t a, size_t b) { return plan[a].work > plan[b].work; });
-        for (size_t i : by_work) {
-            UnitPlan& u = plan[i];
-            if (forced == 1 || u.resident) continue;
+        // automatic: the number of leading units (by work) that may be split
+        size_t n_auto = 0;
+        for (size_t m = 2; m >= 1 && n_auto == 0; --m) {
+            if (by_work.size() < m) continue;
+            bool ok = true;
+            for (size_t r = 0; r < m; ++r) ok = ok && !plan[by_work[r]].resident;
+            const int64_t rest = by_work.size() > m ? plan[by_work[m]].work : 0;
+            if (ok && plan[by_work[m - 1]].work >= 3 * rest) n_auto = m;
+        }
+        for (size_t r = 0; r < by_work.size(); ++r) {
+            UnitPlan& u = plan[by_work[r]];
+            if (forced == 1 || u.resident || (forced == 0 && r >= n_auto)) continue;
             const VbGraph& g = graphs[(size_t)u.group];
             int32_t maxcls = 0;
             for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
@@ -1421,7 +1436,9 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
         }
     });
     if (st != SG_OK) return st;
-    if (err_flag & 6) return SG_EDEVICE;   // a sweep pipeline stalled, or a split unit's barrier timed out
+    // a sweep pipeline stalled, a split unit's barrier timed out, or the VB
+    // sweep kernel found its dynamic LDS away from offset 0
+    if (err_flag & 14) return SG_EDEVICE;
     return (err_flag & 1) ? SG_EPARITY : SG_OK;
 }
 

@@ -75,7 +75,7 @@ struct VbUnit {
     int32_t members;
     int32_t member;
     uint32_t* bar;
-    int* err;                  // bit 2 set when a barrier wait timed out
+    int* err;                  // bit 2: a barrier wait timed out; bit 3: dynamic LDS not at offset 0
 };
 
 // One SK chain (a replica of an instance).

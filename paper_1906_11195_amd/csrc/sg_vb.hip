@@ -65,6 +65,7 @@ struct Sl {
 
 struct VbLds {
     uint32_t* sp;                 // spins, VbLayout words
+    uint32_t sp_lds;              // the same array as a byte offset in LDS
     uint32_t* thr;                // [8][kTab]: 64 - x -> thr[x] >> 16; 0x10000 for x <= 0
     unsigned long long* accs;     // [8]
     int32_t* flag;                // [4]: split units' abort flag
@@ -80,10 +81,11 @@ __host__ __device__ __forceinline__ int32_t vb_batch_chunks(int32_t nch)
     return nch <= 8 ? (8 / nch > 0 ? 8 / nch : 1) : 1;
 }
 
-__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, int32_t sw, int nthr, int32_t nch)
+__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, uint32_t smem_lds, int32_t sw, int nthr, int32_t nch)
 {
     VbLds L;
     L.sp = smem;
+    L.sp_lds = smem_lds;
     L.thr = smem + ((sw + 3) & ~3);
     L.accs = (unsigned long long*)(L.thr + kVbMaxChains * kTab);
     L.flag = (int32_t*)(L.accs + kVbMaxChains);
@@ -263,14 +265,20 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
 
     const bool act = q >= lo && q < hi;
     const int32_t deg = st.r1 - st.r0;   // 0 on inactive lanes
-    const char* spb = (const char*)L.sp;
+    // spin words read through a local-address-space pointer made from the
+    // array's LDS offset (a constant 0 with 8 chain slots), so that the base
+    // is neither kept in a register nor re-read for every neighbour
+    const uint32_t spo = L.sp_lds;
+    auto spw = [&](uint32_t off) -> uint32_t {
+        return *(const __attribute__((address_space(3))) uint32_t*)(size_t)(spo + off);
+    };
     const uint32_t qsh = (uint32_t)q & (uint32_t)(S::P - 1);
     // own word, position q at the field bottoms
-    const uint32_t o0 = act ? *(const uint32_t*)(spb + S::boff((uint32_t)q)) >> qsh : 0u;
+    const uint32_t o0 = act ? spw(S::boff((uint32_t)q)) >> qsh : 0u;
     // bit c P of f: the bond to the neighbour is unsatisfied in chain c
     auto unsat = [&](uint32_t en) {
         const uint32_t sh = en & (uint32_t)(S::P - 1);
-        return (*(const uint32_t*)(spb + S::boff(en)) >> sh) ^ o0 ^ (uint32_t)((int32_t)en >> 31);
+        return (spw(S::boff(en)) >> sh) ^ o0 ^ (uint32_t)((int32_t)en >> 31);
     };
     // per-chain counts of unsatisfied bonds: cA holds P-bit fields (for RPAD 8
     // while every degree of the chunk is below 16), else for RPAD 8 cA / cB
@@ -462,7 +470,7 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
     const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) + (SPLIT ? up->member * Wl : 0));
     const int W = SPLIT ? up->members * Wl : Wl;
     const int32_t sw = up->state_words, nch = up->nch, ncls = up->ncls;
-    const VbLds L = vb_carve(smem, sw, nthr, nch);
+    const VbLds L = vb_carve(smem, RPAD == 8 ? 0u : lds0, sw, nthr, nch);
 
     const SG_G uint32_t* gstate = gl(up->state);
     for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = gstate[w];
@@ -509,7 +517,10 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
 {
     const int tid = threadIdx.x;
     const int32_t nch = up->nch, ncls = up->ncls;
-    const uint64_t key = up->key;
+    // the Philox key is the same for every lane: kept in scalar registers,
+    // so that the per-round keys cost no vector registers
+    const uint64_t key = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(up->key >> 32)) << 32) |
+                         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)up->key);
     const int wl = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront inside the workgroup
     // Philox batches: cursor of the next chunk to draw for, chunks left in
     // the current batch and the batch position of the next chunk
@@ -607,8 +618,15 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
     uint32_t lds0 = (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t*)smem;
-    asm volatile("" : "+s"(lds0));   // an opaque value: the callee cannot re-derive it from the array
     const VbUnit* up = (const VbUnit*)(gl(units) + blockIdx.x);
+    // The 8-slot variant addresses its spins at LDS offset 0, where the
+    // dynamic array starts in a kernel that declares no static LDS (a
+    // constant test: a build where that does not hold reports an error)
+    if (lds0 != 0u) {
+        if (threadIdx.x == 0) atomicOr(up->err, 8);
+        return;
+    }
+    asm volatile("" : "+s"(lds0));   // an opaque value: the callee cannot re-derive it from the array
     const int64_t t0 = *gl(t0p);
     if (up->resident) {
         switch (up->rpad) {
