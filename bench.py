@@ -31,6 +31,8 @@ METRIC = "spin flips/ns at 1 GPU (VB, SK), batched vs plain; p50/p99 run latency
 HBM_PEAK_GBS = 8000.0
 HBM_PEAK_BPS = HBM_PEAK_GBS * 1e9
 MFMA_INT8_PEAK_OPS = 5.0e15   # dense int8 MFMA, MI355X
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def log(msg):
@@ -81,21 +83,37 @@ def vb_kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def _profile_values(prefix: str):
+    """The `prefix`* key: value lines of the committed VB profile, or None when
+    the kernel sources have changed since its counters were taken."""
+    try:
+        with open(PROFILE_VB) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines()
+                      if line.startswith(prefix) and ": " in line)
+    except OSError:
+        return None
+    if kv.get(prefix + "kernel_digest", "").strip() != vb_kernel_digest():
+        return None
+    return kv
+
+
 def profiled_traffic(sweeps_per_launch: float):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE passes
     (already scaled by the copy-kernel calibration), or None when the kernel
     sources have changed since the counters were taken."""
-    try:
-        with open(PROFILE_VB) as fh:
-            kv = dict(line.split(": ", 1) for line in fh.read().splitlines()
-                      if line.startswith("traffic_") and ": " in line)
-    except OSError:
-        return None
-    if kv.get("traffic_kernel_digest", "").strip() != vb_kernel_digest():
+    kv = _profile_values("traffic_")
+    if kv is None:
         return None
     fetch = float(kv["traffic_fetch_kib_per_sweep"]) * 1024.0 * sweeps_per_launch
     write = float(kv["traffic_write_kib_per_launch"]) * 1024.0
     return int(fetch + write)
+
+
+def profiled_valu_per_update():
+    """VALU wave-instructions per chain-update from the committed SQ_INSTS_VALU
+    pass, or None when the kernel sources have changed since."""
+    kv = _profile_values("issue_")
+    return None if kv is None else float(kv["issue_valu_per_update"])
 
 
 def run_vb_batched(args, torch, sg, workloads):
@@ -143,6 +161,15 @@ def run_vb_batched(args, torch, sg, workloads):
     launch_ms = sweep_ms / (args.steps * launches_per_step)
     launch_bytes = bytes_per_sweep * S / launches_per_step
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    # the kernel's own ceiling: VALU issue (one wave64 instruction per SIMD
+    # every 4 cycles), with the instructions per chain-update from the profile
+    vpu = profiled_valu_per_update()
+    valu_issue = None
+    if vpu is not None:
+        rate = n_total * S / launches_per_step / (launch_ms * 1e-3)
+        valu_issue = dict(achieved=round(rate * vpu / 1e9, 1), peak=round(VALU_ISSUE_PEAK / 1e9, 1),
+                          unit="G wave-instructions/s", frac=round(rate * vpu / VALU_ISSUE_PEAK, 4),
+                          per_update=vpu)
     return dict(
         value=updates / (elapsed * 1e9), elapsed=elapsed, updates=updates,
         sweep_kernel_updates_per_ns=updates / (sweep_ms * 1e6),
@@ -151,7 +178,8 @@ def run_vb_batched(args, torch, sg, workloads):
                       frac=round(achieved / HBM_PEAK_GBS, 4),
                       traffic=profiled_traffic(S / launches_per_step), traffic_unit="bytes per launch",
                       kernel="vb_sweep_kernel", launch_ms=round(launch_ms, 4),
-                      bytes_per_launch=int(launch_bytes), bytes_per_update=round(bytes_per_sweep / n_total, 3)),
+                      bytes_per_launch=int(launch_bytes), bytes_per_update=round(bytes_per_sweep / n_total, 3),
+                      valu_issue=valu_issue),
         ms_per_step=elapsed * 1e3 / args.steps, t_done=res["t_done"])
 
 

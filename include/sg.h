@@ -159,10 +159,10 @@ typedef void (*sg_free_fn)(void* ptr, size_t bytes, void* user);
  *                   automatic.  Has no effect on any result.
  *  split_members    VB: a large graph's unit can be spread over several
  *                   workgroups that exchange each colour class's spins through
- *                   HBM at a device-scope barrier.  0 = automatic (at most
- *                   the two largest units, each far above one CU's share of
- *                   the batch and at least three times the work of every
- *                   unit left whole), 1 = never, k >= 2 =
+ *                   HBM at a device-scope barrier.  0 = automatic (the
+ *                   units above twice one CU's share of the batch's work,
+ *                   when no unit left whole would outlast them), 1 = never,
+ *                   k >= 2 =
  *                   k workgroups for every unit with at least 2 k chunks of
  *                   64 positions per wavefront in its largest colour class.
  *                   Has no effect on any result; a barrier that times out

@@ -783,14 +783,17 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     // batch's work is spread over several workgroups (members) that meet at a
     // device-scope barrier after every colour class.  Each member keeps at
     // least two 64-position chunks per wavefront of the largest class, and
-    // the members of all split units of a context use at most a quarter of
-    // the CUs, so that they can all be resident at once next to other work.
-    // The barriers' device-scope fences slow every workgroup that shares the
-    // members' caches, so the automatic choice splits at most two units, and
-    // only units with at least three times the work of the largest unit left
-    // whole: then they alone set the launch's duration (measured with 65536
-    // spins and 6 chains per graph: 1 or 2 graphs, 106 -> 53 or 66 us per
-    // sweep; 8 to 128 equal graphs, 106 -> 136 to 225 us when split).
+    // the members of all split units of a context use at most half of the
+    // CUs, so that they can all be resident at once next to other work.
+    // Splitting shortens a launch only if no unit left whole outlasts the
+    // split ones, so the automatic choice splits the units far above a CU's
+    // share (by work) only when all of them get at least two members, or
+    // else the largest group of them with three times the work of every unit
+    // left whole, and it shares the member budget evenly among them
+    // (measured with 65536 spins and 6 chains per graph, us per sweep: 1 graph
+    // 106 -> 36, 4 graphs 107 -> 43, 8 graphs 107 -> 54, 16 graphs 107 -> 59,
+    // 32 graphs 107 -> 65, 64 graphs 109 -> 85; 128 or more equal graphs stay
+    // whole).
     // opts.split_members: 0 automatic, 1 never, k >= 2 every unit that has
     // the chunks for k members (tests, tuning).  No effect on any result.
     {
@@ -800,20 +803,28 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         int64_t total = 0;
         for (const auto& u : plan) total += u.work;
         const int64_t share = std::max<int64_t>(1, total / std::max(1, n_cu));
-        int budget = n_cu / 4;
+        int budget = n_cu / 2;
         std::vector<size_t> by_work(plan.size());
         for (size_t i = 0; i < plan.size(); ++i) by_work[i] = i;
         std::stable_sort(by_work.begin(), by_work.end(),
                          [&](size_t a, size_t b) { return plan[a].work > plan[b].work; });
-        // automatic: the number of leading units (by work) that may be split
         size_t n_auto = 0;
-        for (size_t m = 2; m >= 1 && n_auto == 0; --m) {
-            if (by_work.size() < m) continue;
-            bool ok = true;
-            for (size_t r = 0; r < m; ++r) ok = ok && !plan[by_work[r]].resident;
-            const int64_t rest = by_work.size() > m ? plan[by_work[m]].work : 0;
-            if (ok && plan[by_work[m - 1]].work >= 3 * rest) n_auto = m;
+        if (forced == 0) {
+            size_t cand = 0;
+            while (cand < by_work.size() && !plan[by_work[cand]].resident && plan[by_work[cand]].work >= 2 * share)
+                ++cand;
+            for (size_t m = std::min(cand, (size_t)(budget / 2)); m >= 1; --m) {
+                const int64_t rest = by_work.size() > m ? plan[by_work[m]].work : 0;
+                if (m == cand || plan[by_work[m - 1]].work >= 3 * rest) {
+                    n_auto = m;
+                    break;
+                }
+            }
         }
+        // members per unit: with few split units many members pay, with many
+        // the per-class barriers of thinly spread members cost more than
+        // they save (16 graphs: 4 members 59 us per sweep, 8 members 73 us)
+        const int per_unit = n_auto == 0 ? 0 : std::min(budget / (int)n_auto, n_auto <= 2 ? 16 : n_auto <= 8 ? 8 : 4);
         for (size_t r = 0; r < by_work.size(); ++r) {
             UnitPlan& u = plan[by_work[r]];
             if (forced == 1 || u.resident || (forced == 0 && r >= n_auto)) continue;
@@ -821,7 +832,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
             int32_t maxcls = 0;
             for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
             const int64_t chunk_cap = ((maxcls + 63) / 64) / (2 * (u.threads / 64));
-            int64_t want = forced >= 2 ? forced : std::min<int64_t>(16, u.work / share);
+            int64_t want = forced >= 2 ? forced : std::min<int64_t>({16, u.work / share, (int64_t)per_unit});
             want = std::min<int64_t>(want, std::min<int64_t>(chunk_cap, budget));
             if (want >= 2) {
                 u.members = (int)want;

@@ -328,11 +328,16 @@ __device__ bool vb_exchange(const VbUnit* __restrict__ up, const VbLds& L, int32
                             uint32_t target)
 {
     using S = Sl<RPAD>;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // One thread fences for the workgroup (as a grid barrier does): the
+    // workgroup barrier orders every wavefront's write-through stores before
+    // its device-scope release, and its device-scope acquire before the
+    // read-back below.  (A fence in every wavefront wrote back and invalidated
+    // the shared caches once per wavefront, slowing every workgroup on them.)
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t* bar = up->bar;
         int32_t ab = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t start = wall_clock64();
         while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -348,11 +353,11 @@ __device__ bool vb_exchange(const VbUnit* __restrict__ up, const VbLds& L, int32
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         L.flag[0] = ab;
     }
     __syncthreads();
     if (L.flag[0] != 0) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const SG_G uint32_t* gs = gl(up->state);
     const int32_t w0 = lo >> S::LP, w1 = hi > lo ? ((hi - 1) >> S::LP) : w0 - 1;
     for (int32_t w = w0 + (int32_t)threadIdx.x; w <= w1; w += (int32_t)blockDim.x) L.sp[w] = gs[w];
