@@ -259,6 +259,9 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
                                          uint64_t key, const uint32_t* gx, uint32_t* acc)
 {
     using S = Sl<RPAD>;
+    // adjacency resident in LDS: such units are small and bound by the
+    // latency of a chunk, not by instruction issue
+    constexpr bool LAT = !__is_same(PE, const SG_G uint32_t*);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int32_t q = st.q;
@@ -286,10 +289,26 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
     uint32_t cA = 0, cB = 0;
     const bool wide = RPAD == 8 && __any(deg > 15);
     if (!wide) {
+        if (LAT) {
+            // every prefetched neighbour word is read before any is counted,
+            // so that the LDS round trips overlap; a lane past its degree
+            // reads its own word, whose contribution is zero (an inactive
+            // lane reads word 0: its counts stay below 9 and are not used)
+            const uint32_t qa = act ? (uint32_t)q : 0u;
+            uint32_t wv[kDMax];
 #pragma unroll
-        for (int d = 0; d < kDMax; ++d) {
-            if (!__any(d < deg)) break;
-            if (d < deg) cA += unsat(st.e[d]) & S::M;
+            for (int d = 0; d < kDMax; ++d) {
+                const uint32_t en = d < deg ? st.e[d] : qa;
+                wv[d] = (spw(S::boff(en)) >> (en & (uint32_t)(S::P - 1))) ^ (uint32_t)((int32_t)en >> 31);
+            }
+#pragma unroll
+            for (int d = 0; d < kDMax; ++d) cA += (wv[d] ^ o0) & S::M;
+        } else {
+#pragma unroll
+            for (int d = 0; d < kDMax; ++d) {
+                if (!__any(d < deg)) break;
+                if (d < deg) cA += unsat(st.e[d]) & S::M;
+            }
         }
         for (int32_t d = kDMax; d < deg; ++d) cA += unsat(ent[st.r0 + d]) & S::M;
     } else {
