@@ -73,3 +73,17 @@ def test_automatic_split_of_one_large_graph():
     res = run_lib(descs, [6, 6], 8)
     for i, d in enumerate(descs):
         assert_instance_equal(res, i, oracle_vb(d, 12, 8), label="auto i=%d" % i)
+
+
+def test_automatic_split_of_several_equal_graphs():
+    # equal graphs far above a CU's share are all split by the automatic plan
+    # (several split units meet at their barriers in the same launches); the
+    # result is the unsplit run's and the oracle's
+    require_gpu()
+    descs = [sg.VbDesc(n=20011, T=0.8, seed=9, instance_id=k, graph_id=k, c=4.0) for k in range(3)]
+    chunks = [4, 7]
+    res = run_lib(descs, chunks, 16, threads_per_unit=64, split_members=0)
+    ref = run_lib(descs, chunks, 16, threads_per_unit=64, split_members=1)
+    assert_same(res, ref, "auto split vs unsplit")
+    for i, d in enumerate(descs):
+        assert_instance_equal(res, i, oracle_vb(d, sum(chunks), 16), label="auto equal i=%d" % i)
