@@ -295,12 +295,16 @@ def run_cpu_baseline(args, workloads):
     threads = max(1, min(16, cores))
     descs = workloads.vb_batched()[:threads]
     graphs = [oracle.vb_instance(d.n, d.c, d.seed, d.graph_id) for d in descs]
-    # calibrate on one sweep of one instance
-    t0 = time.perf_counter()
+    # calibrate the cost of one sweep of one instance: the difference of a
+    # 5-sweep and a 1-sweep run (each run also builds the instance's tables)
     eu, ev, J = graphs[0]
-    oracle.vb_run(descs[0].n, eu, ev, J, descs[0].T, descs[0].seed, descs[0].instance_id, 2, 1, 1)
-    one = time.perf_counter() - t0
-    sweeps = int(max(2, min(4096, args.cpu_seconds / max(one, 1e-3))))
+    cost = []
+    for n_sw in (1, 5):
+        t0 = time.perf_counter()
+        oracle.vb_run(descs[0].n, eu, ev, J, descs[0].T, descs[0].seed, descs[0].instance_id, 2, n_sw, n_sw)
+        cost.append(time.perf_counter() - t0)
+    one = max((cost[1] - cost[0]) / 4.0, 1e-4)
+    sweeps = int(max(2, min(4096, args.cpu_seconds / one)))
 
     def job(i):
         d = descs[i]
