@@ -269,8 +269,8 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
     const bool act = q >= lo && q < hi;
     const int32_t deg = st.r1 - st.r0;   // 0 on inactive lanes
     // spin words read through a local-address-space pointer made from the
-    // array's LDS offset (a constant 0 with 8 chain slots), so that the base
-    // is neither kept in a register nor re-read for every neighbour
+    // array's LDS offset (the constant 0), so that the base is neither kept
+    // in a register nor re-read for every neighbour
     const uint32_t spo = L.sp_lds;
     auto spw = [&](uint32_t off) -> uint32_t {
         return *(const __attribute__((address_space(3))) uint32_t*)(size_t)(spo + off);
@@ -494,7 +494,7 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
     const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) + (SPLIT ? up->member * Wl : 0));
     const int W = SPLIT ? up->members * Wl : Wl;
     const int32_t sw = up->state_words, nch = up->nch, ncls = up->ncls;
-    const VbLds L = vb_carve(smem, RPAD == 8 ? 0u : lds0, sw, nthr, nch);
+    const VbLds L = vb_carve(smem, 0u, sw, nthr, nch);
 
     const SG_G uint32_t* gstate = gl(up->state);
     for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = gstate[w];
@@ -643,7 +643,7 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
     extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
     uint32_t lds0 = (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t*)smem;
     const VbUnit* up = (const VbUnit*)(gl(units) + blockIdx.x);
-    // The 8-slot variant addresses its spins at LDS offset 0, where the
+    // The sweep functions read the spin words at LDS offset 0, where the
     // dynamic array starts in a kernel that declares no static LDS (a
     // constant test: a build where that does not hold reports an error)
     if (lds0 != 0u) {
