@@ -323,13 +323,15 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
     const uint32_t fl = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key, acc);
     // write the flips back: every lane XORs its flips into its spin word (the
     // P lanes of a word are in this wavefront's chunk, nothing else writes it)
-    if (fl) atomicXor(&L.sp[(uint32_t)q >> S::LP], fl << qsh);
+    if (fl)
+        __atomic_fetch_xor((__attribute__((address_space(3))) uint32_t*)(size_t)(spo + ((uint32_t)q >> S::LP) * 4u),
+                           fl << qsh, __ATOMIC_RELAXED);
     if (SPLIT) {
         // a member of a split unit also writes the chunk's words through to HBM
         wave_sync();
         if (lane < 64 / S::P) {
             const uint32_t wi = ((uint32_t)(q - lane) >> S::LP) + (uint32_t)lane;
-            if (wi < (uint32_t)up->state_words) gl(up->state)[wi] = L.sp[wi];
+            if (wi < (uint32_t)up->state_words) gl(up->state)[wi] = spw(wi * 4u);
         }
     }
 }
