@@ -260,6 +260,34 @@ def run_uneven(args, torch, sg, workloads):
                 updates_per_ns=upd / (el * 1e9), create_s=round(create_s, 2))
 
 
+def run_rrbg(args, torch, sg, workloads):
+    """The paper's graph ensemble: 256 random regular bipartite graphs of degree 4
+    (N = 65536, +-1 couplings, explicit edge lists) x 3 temperatures x 2
+    replicas, the temperatures of a graph sharing its arrays (one unit per
+    graph, as in the batched leg)."""
+    t0 = time.perf_counter()
+    descs = workloads.vb_rrbg_batched()
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx = sg.sg_create_vb(descs, t_max=workloads.VB_BATCHED_SWEEPS)
+    create_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    sg.sg_sweep(ctx, 64, stream)
+    torch.cuda.synchronize()
+    S = args.rrbg_sweeps
+    t0 = time.perf_counter()
+    sg.sg_sweep(ctx, S, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+    sg.sg_free(ctx)
+    upd = sum(d.n for d in descs) * 2 * S
+    return dict(workload="VB RRBG: 256 random regular bipartite graphs (degree 4, N=65536, J=+-1) x "
+                         "T{0.6,0.8,1.2} x 2 replicas; sweeps 64..%d" % (64 + S),
+                updates_per_ns=upd / (el * 1e9), generate_s=round(gen_s, 2), create_s=round(create_s, 2),
+                t_done=res["t_done"])
+
+
 def run_serving(args, torch, sg, workloads):
     """Serving: Poisson arrivals, 70% VB (N in [2^12, 2^20]) / 30% SK (N in
     [512, 8192]), T ~ U[0.5, 0.9]; run lengths reduced to 2^8..2^10 sweeps so
@@ -334,9 +362,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-vb", action="store_true", help="the batched VB leg only (same as --legs vb)")
-    ap.add_argument("--legs", default="vb,plain,sk,uneven,serving",
-                    help="comma-separated legs to run besides the headline: plain, sk, uneven, serving")
+    ap.add_argument("--legs", default="vb,plain,sk,uneven,rrbg,serving",
+                    help="comma-separated legs to run besides the headline: plain, sk, uneven, rrbg, serving")
     ap.add_argument("--uneven-sweeps", type=int, default=128)
+    ap.add_argument("--rrbg-sweeps", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
@@ -370,7 +399,7 @@ def main():
     sg.library()
     vb = run_vb_batched(args, torch, sg, workloads)
     log("VB batched: %.1f updates/ns" % vb["value"])
-    plain = sk = uneven = serve = None
+    plain = sk = uneven = rrbg = serve = None
     legs = set() if args.only_vb else set(x.strip() for x in args.legs.split(","))
     if "plain" in legs:
         plain = run_vb_plain(args, torch, sg, workloads)
@@ -381,6 +410,9 @@ def main():
     if "uneven" in legs:
         uneven = run_uneven(args, torch, sg, workloads)
         log("VB uneven: %.1f updates/ns" % uneven["updates_per_ns"])
+    if "rrbg" in legs:
+        rrbg = run_rrbg(args, torch, sg, workloads)
+        log("VB RRBG: %.1f updates/ns" % rrbg["updates_per_ns"])
     if "serving" in legs:
         serve = run_serving(args, torch, sg, workloads)
         log("serving: p50 %.1f ms, p99 %.1f ms" % (serve.get("p50_ms", 0), serve.get("p99_ms", 0)))
@@ -417,6 +449,7 @@ def main():
         "plain": plain,
         "sk": sk,
         "uneven": uneven,
+        "rrbg": rrbg,
         "serving": serve,
     }
     print(json.dumps(out), flush=True)

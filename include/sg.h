@@ -102,7 +102,9 @@ typedef struct sg_ctx sg_ctx;
  *  T          temperature, T >= 0, +inf allowed.
  *  seed       Philox key.  instance_id keys the dynamics; graph_id keys the
  *             generated graph.  Instances with equal (n, c, seed, graph_id)
- *             and no explicit edges share one graph and its couplings.
+ *             and no explicit edges share one graph and its couplings, and
+ *             so do instances that pass the same edges and J arrays (equal
+ *             pointers, n and n_edges).
  *  n_replicas 1 <= n_replicas <= 8, equal for all instances of a context.
  *  start      SG_START_*; s0 is host int8[n_replicas][n] of +-1 in vertex
  *             order when start == SG_START_GIVEN. */

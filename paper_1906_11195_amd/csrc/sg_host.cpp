@@ -689,12 +689,19 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         }
     };
     std::unordered_map<Key, int32_t, KeyHash> gid_of;
+    // explicit graphs are shared by the instances that pass the same arrays
+    std::map<std::tuple<int64_t, int64_t, const int32_t*, const int8_t*>, int32_t> explicit_of;
     std::vector<int32_t> first_inst;   // representative desc per group
     c->group_of_inst.resize((size_t)count);
     for (int32_t i = 0; i < count; ++i) {
         if (d[i].edges) {
-            c->group_of_inst[(size_t)i] = (int32_t)first_inst.size();
-            first_inst.push_back(i);
+            const auto ek = std::make_tuple((int64_t)d[i].n, d[i].n_edges, d[i].edges, d[i].J);
+            auto it = explicit_of.find(ek);
+            if (it == explicit_of.end()) {
+                it = explicit_of.emplace(ek, (int32_t)first_inst.size()).first;
+                first_inst.push_back(i);
+            }
+            c->group_of_inst[(size_t)i] = it->second;
             continue;
         }
         uint64_t cb;

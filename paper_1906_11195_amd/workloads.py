@@ -20,6 +20,10 @@ couplings, SI sections on the SK model and on the bipartite graph).
   serving     Poisson arrivals; 70 % VB with N log-uniform in [2^12, 2^20],
               30 % SK with N log-uniform in [512, 8192]; T ~ U[0.5, 0.9];
               2^k sweeps, k uniform in {12..16}; seed 5.
+  VB RRBG     the paper's graph ensemble (SI, bipartite-graph section): 256
+              random regular bipartite graphs of degree 4, N = 65536, +-1
+              couplings, x T in {0.6, 0.8, 1.2} x 2 replicas, seed 6; the
+              three temperatures of a graph pass the same edge arrays.
 """
 from __future__ import annotations
 
@@ -90,4 +94,70 @@ def serving_requests(count: int, rate: float, seed: int = 5) -> List[Request]:
         T = float(rng.uniform(0.5, 0.9))
         sweeps = 1 << int(rng.integers(12, 17))
         out.append(Request(rid, t, kind, n, T, sweeps))
+    return out
+
+
+def random_regular_edges(n: int, z: int, seed: int, bipartite: bool = False):
+    """Edge list and +-1 couplings of a random z-regular graph on n vertices
+    (bipartite: every edge joins {0 .. n/2 - 1} to {n/2 .. n - 1}).  The
+    configuration model pairs the z stubs of every vertex at random (for the
+    bipartite graph, the stubs of one half with those of the other); each
+    self-loop or repeated edge is then removed by exchanging an endpoint with
+    a randomly chosen other edge, which keeps every degree and the
+    bipartition.  Returns (int32 [m, 2], int8 [m]) with m = n z / 2."""
+    rng = np.random.default_rng(seed)
+    if bipartite:
+        if n % 2:
+            raise ValueError("bipartite graph needs an even n")
+        h = n // 2
+        a = rng.permutation(np.repeat(np.arange(h, dtype=np.int64), z))
+        b = rng.permutation(np.repeat(np.arange(h, n, dtype=np.int64), z))
+        e = np.stack([a, b], axis=1)
+    else:
+        if (n * z) % 2:
+            raise ValueError("n z must be even")
+        e = rng.permutation(np.repeat(np.arange(n, dtype=np.int64), z)).reshape(-1, 2)
+    m = len(e)
+
+    def code(u, v):
+        return np.minimum(u, v) * n + np.maximum(u, v)
+
+    codes = code(e[:, 0], e[:, 1])
+    _, first = np.unique(codes, return_index=True)
+    bad = np.ones(m, bool)
+    bad[first] = False
+    bad |= e[:, 0] == e[:, 1]
+    seen = {}
+    for i, cd in enumerate(codes.tolist()):
+        if not bad[i]:
+            seen[cd] = i
+    for i in np.flatnonzero(bad).tolist():
+        while True:
+            j = int(rng.integers(m))
+            if j == i or bad[j]:
+                continue
+            u, v = int(e[i, 0]), int(e[i, 1])
+            x, y = int(e[j, 0]), int(e[j, 1])
+            # (u, v), (x, y) -> (u, y), (x, v): degrees and halves unchanged
+            c1, c2 = int(code(u, y)), int(code(x, v))
+            if u == y or x == v or c1 == c2 or c1 in seen or c2 in seen:
+                continue
+            del seen[int(codes[j])]
+            e[i, 1], e[j, 1] = y, v
+            codes[i], codes[j] = c1, c2
+            seen[c1], seen[c2] = i, j
+            bad[i] = False
+            break
+    J = np.where(rng.random(m) < 0.5, -1, 1).astype(np.int8)
+    return e.astype(np.int32), J
+
+
+def vb_rrbg_batched(n_graphs: int = 256, n: int = 65536, z: int = 4, temps=(0.6, 0.8, 1.2),
+                    seed: int = 6) -> List[VbDesc]:
+    out = []
+    for s in range(n_graphs):
+        edges, J = random_regular_edges(n, z, seed * 1000003 + s, bipartite=True)
+        for tau, T in enumerate(temps):
+            out.append(VbDesc(n=n, T=T, seed=seed, instance_id=len(temps) * s + tau, graph_id=s,
+                              n_replicas=2, edges=edges, J=J))
     return out
