@@ -104,50 +104,67 @@ def random_regular_edges(n: int, z: int, seed: int, bipartite: bool = False):
     bipartite graph, the stubs of one half with those of the other); each
     self-loop or repeated edge is then removed by exchanging an endpoint with
     a randomly chosen other edge, which keeps every degree and the
-    bipartition.  Returns (int32 [m, 2], int8 [m]) with m = n z / 2."""
+    bipartition (a small dense graph whose repair stalls is paired again).
+    Returns (int32 [m, 2], int8 [m]) with m = n z / 2."""
+    if z < 1 or (z > n // 2 if bipartite else z >= n):
+        raise ValueError("no simple %d-regular %sgraph on %d vertices" % (z, "bipartite " if bipartite else "", n))
     rng = np.random.default_rng(seed)
-    if bipartite:
-        if n % 2:
-            raise ValueError("bipartite graph needs an even n")
-        h = n // 2
-        a = rng.permutation(np.repeat(np.arange(h, dtype=np.int64), z))
-        b = rng.permutation(np.repeat(np.arange(h, n, dtype=np.int64), z))
-        e = np.stack([a, b], axis=1)
-    else:
-        if (n * z) % 2:
-            raise ValueError("n z must be even")
-        e = rng.permutation(np.repeat(np.arange(n, dtype=np.int64), z)).reshape(-1, 2)
-    m = len(e)
+    if bipartite and n % 2:
+        raise ValueError("bipartite graph needs an even n")
+    if not bipartite and (n * z) % 2:
+        raise ValueError("n z must be even")
 
     def code(u, v):
         return np.minimum(u, v) * n + np.maximum(u, v)
 
-    codes = code(e[:, 0], e[:, 1])
-    _, first = np.unique(codes, return_index=True)
-    bad = np.ones(m, bool)
-    bad[first] = False
-    bad |= e[:, 0] == e[:, 1]
-    seen = {}
-    for i, cd in enumerate(codes.tolist()):
-        if not bad[i]:
-            seen[cd] = i
-    for i in np.flatnonzero(bad).tolist():
-        while True:
-            j = int(rng.integers(m))
-            if j == i or bad[j]:
-                continue
-            u, v = int(e[i, 0]), int(e[i, 1])
-            x, y = int(e[j, 0]), int(e[j, 1])
-            # (u, v), (x, y) -> (u, y), (x, v): degrees and halves unchanged
-            c1, c2 = int(code(u, y)), int(code(x, v))
-            if u == y or x == v or c1 == c2 or c1 in seen or c2 in seen:
-                continue
-            del seen[int(codes[j])]
-            e[i, 1], e[j, 1] = y, v
-            codes[i], codes[j] = c1, c2
-            seen[c1], seen[c2] = i, j
-            bad[i] = False
+    def attempt():
+        # one pairing and its repair; None when an exchange cannot be found
+        # (small dense graphs), and the pairing is drawn again
+        if bipartite:
+            h = n // 2
+            a = rng.permutation(np.repeat(np.arange(h, dtype=np.int64), z))
+            b = rng.permutation(np.repeat(np.arange(h, n, dtype=np.int64), z))
+            e = np.stack([a, b], axis=1)
+        else:
+            e = rng.permutation(np.repeat(np.arange(n, dtype=np.int64), z)).reshape(-1, 2)
+        m = len(e)
+        codes = code(e[:, 0], e[:, 1])
+        _, first = np.unique(codes, return_index=True)
+        bad = np.ones(m, bool)
+        bad[first] = False
+        bad |= e[:, 0] == e[:, 1]
+        seen = {}
+        for k, cd in enumerate(codes.tolist()):
+            if not bad[k]:
+                seen[cd] = k
+        for i in np.flatnonzero(bad).tolist():
+            for _ in range(4096):
+                j = int(rng.integers(m))
+                if j == i or bad[j]:
+                    continue
+                u, v = int(e[i, 0]), int(e[i, 1])
+                x, y = int(e[j, 0]), int(e[j, 1])
+                # (u, v), (x, y) -> (u, y), (x, v): degrees and halves unchanged
+                c1, c2 = int(code(u, y)), int(code(x, v))
+                if u == y or x == v or c1 == c2 or c1 in seen or c2 in seen:
+                    continue
+                del seen[int(codes[j])]
+                e[i, 1], e[j, 1] = y, v
+                codes[i], codes[j] = c1, c2
+                seen[c1], seen[c2] = i, j
+                bad[i] = False
+                break
+            else:
+                return None
+        return e
+
+    for _ in range(10000):
+        e = attempt()
+        if e is not None:
             break
+    else:
+        raise RuntimeError("no simple %d-regular graph found on %d vertices" % (z, n))
+    m = len(e)
     J = np.where(rng.random(m) < 0.5, -1, 1).astype(np.int8)
     return e.astype(np.int32), J
 

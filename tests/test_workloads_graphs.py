@@ -38,3 +38,15 @@ def test_rrbg_recipe_shares_arrays_between_temperatures():
     assert len(descs) == 6
     assert descs[0].edges is descs[1].edges is descs[2].edges and descs[0].J is descs[2].J
     assert descs[3].edges is not descs[0].edges
+
+
+@pytest.mark.parametrize("n,z,bipartite", [(4, 4, False), (8, 5, True), (7, 3, False), (7, 2, True)])
+def test_impossible_regular_graphs_are_refused(n, z, bipartite):
+    with pytest.raises(ValueError):
+        W.random_regular_edges(n, z, seed=1, bipartite=bipartite)
+
+
+def test_dense_regular_graph_is_found():
+    # the complete graph K5 is the only 4-regular simple graph on 5 vertices
+    e, J = W.random_regular_edges(5, 4, seed=2)
+    _check(5, 4, e, J, False)
