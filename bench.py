@@ -310,6 +310,18 @@ def run_serving(args, torch, sg, workloads):
     return st
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first `model name` line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def run_cpu_baseline(args, workloads):
     """The oracle, as it stands, on a bounded sample of the same workload:
     `threads` instances of the batched configuration (N = 65536, 2 replicas)
@@ -320,7 +332,11 @@ def run_cpu_baseline(args, workloads):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    threads = max(1, min(16, cores))
+    # one oracle instance per core of this process's CPU share: the cores it
+    # may run on, limited by the thread allotment the host sets for it
+    # (OMP_NUM_THREADS), which is its share of a machine shared by several GPUs
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    threads = max(1, min(cores, int(share))) if share.isdigit() and int(share) > 0 else max(1, cores)
     descs = workloads.vb_batched()[:threads]
     graphs = [oracle.vb_instance(d.n, d.c, d.seed, d.graph_id) for d in descs]
     # calibrate the cost of one sweep of one instance: the difference of a
@@ -345,8 +361,9 @@ def run_cpu_baseline(args, workloads):
     el = time.perf_counter() - t0
     upd = threads * 2 * 65536 * sweeps
     return dict(value=upd / (el * 1e9), unit="attempted spin updates/ns", cores=threads, kind="oracle",
+                host_cpus=cores, cpu_model=cpu_model(),
                 sample="%d instances of the batched VB workload (N=65536, 2 replicas), %d sweeps each, "
-                       "one instance per thread; %.1f s" % (threads, sweeps, el))
+                       "one instance per thread (%d host CPUs visible); %.1f s" % (threads, sweeps, cores, el))
 
 
 def main():

@@ -104,7 +104,8 @@ typedef struct sg_ctx sg_ctx;
  *             generated graph.  Instances with equal (n, c, seed, graph_id)
  *             and no explicit edges share one graph and its couplings, and
  *             so do instances that pass the same edges and J arrays (equal
- *             pointers, n and n_edges).
+ *             pointers, n, n_edges and seed); instances with other seeds get
+ *             units of their own.
  *  n_replicas 1 <= n_replicas <= 8, equal for all instances of a context.
  *  start      SG_START_*; s0 is host int8[n_replicas][n] of +-1 in vertex
  *             order when start == SG_START_GIVEN. */
@@ -240,6 +241,17 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream);
  * work), never for other contexts, and releases everything it owns.
  * sg_free(NULL) does nothing. */
 void sg_free(sg_ctx* c);
+
+/* Fault injection for tests of the SK integrity check (the exact
+ * recomputation of the local fields every recompute_period sweeps, SI SK
+ * section: the force computation is the path's critical part).  Adds `delta`
+ * to the incremental local field H_i of chain (instance, replica) between
+ * sweeps, after waiting for the context's streams.  The next recomputation
+ * finds the mismatch and overwrites the field with the exact value, and
+ * sg_measure returns SG_EPARITY from then on; the trajectory after the
+ * corruption is not the method's.  SG_EINVAL for a VB context or indices out
+ * of range. */
+sg_status sg_sk_corrupt_field(sg_ctx* c, int32_t instance, int32_t replica, int64_t i, int32_t delta);
 
 /* Static description of a status code. */
 const char* sg_strerror(sg_status s);

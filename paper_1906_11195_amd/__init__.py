@@ -28,7 +28,7 @@ MEASURE_OBS, MEASURE_SPINS = 1, 2
 OPT_AUTOTUNE, OPT_GRAPH = 1, 2
 
 EXPORTS = ("sg_create_vb", "sg_create_sk", "sg_sweep", "sg_measure", "sg_free", "sg_strerror",
-           "sg_vb_inspect", "sg_sk_inspect")
+           "sg_vb_inspect", "sg_sk_inspect", "sg_sk_corrupt_field")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -103,6 +103,8 @@ def library() -> ctypes.CDLL:
         lib.sg_vb_inspect.restype = ctypes.c_int32
         lib.sg_sk_inspect.argtypes = [P, P, P]
         lib.sg_sk_inspect.restype = ctypes.c_int32
+        lib.sg_sk_corrupt_field.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
+        lib.sg_sk_corrupt_field.restype = ctypes.c_int32
         _lib = lib
         return lib
 
@@ -354,3 +356,9 @@ def sg_sk_inspect(d: SkDesc):
     thr = np.zeros(d.n, np.uint64)
     _check(library().sg_sk_inspect(ctypes.byref(s), _p(J), _p(thr)), "sg_sk_inspect")
     return J, thr
+
+
+def sg_sk_corrupt_field(ctx: Context, instance: int, replica: int, i: int, delta: int) -> None:
+    """Fault injection for tests of the SK integrity check (see include/sg.h)."""
+    _check(library().sg_sk_corrupt_field(ctx.ptr, int(instance), int(replica), int(i), int(delta)),
+           "sg_sk_corrupt_field")

@@ -20,6 +20,7 @@
 
 #include "sg.h"
 #include "sg_internal.h"
+#include "sg_ledger.h"
 #include "sg_philox.h"
 
 using namespace sg;
@@ -347,6 +348,10 @@ struct Arena {
 
 }  // namespace
 
+namespace {
+SplitLedger g_split_ledger;   // split-unit members held per device, all contexts
+}  // namespace
+
 struct sg_ctx {
     int kind = 0;   // 0 VB, 1 SK
     int device = 0;
@@ -399,6 +404,7 @@ struct sg_ctx {
     int64_t* t_dev = nullptr;             // device counter of sweeps done
     uint32_t* bars_d = nullptr;           // split units' barrier words, 2 per unit
     int n_bar = 0;
+    int split_held = 0;                   // members reserved in the process-wide ledger
     bool use_graph = false;
     hipStream_t capture_stream = nullptr; // for capturing when the caller uses the null stream
     std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;   // chunk length -> executable
@@ -436,6 +442,8 @@ struct sg_ctx {
     }
     void release()
     {
+        g_split_ledger.release(device, split_held);
+        split_held = 0;
         for (auto& gx : graphs) (void)hipGraphExecDestroy(gx.second);
         graphs.clear();
         for (auto& G : groups) {
@@ -690,12 +698,13 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     };
     std::unordered_map<Key, int32_t, KeyHash> gid_of;
     // explicit graphs are shared by the instances that pass the same arrays
-    std::map<std::tuple<int64_t, int64_t, const int32_t*, const int8_t*>, int32_t> explicit_of;
+    // with the same seed (a unit's chains share one Philox key)
+    std::map<std::tuple<int64_t, int64_t, const int32_t*, const int8_t*, uint64_t>, int32_t> explicit_of;
     std::vector<int32_t> first_inst;   // representative desc per group
     c->group_of_inst.resize((size_t)count);
     for (int32_t i = 0; i < count; ++i) {
         if (d[i].edges) {
-            const auto ek = std::make_tuple((int64_t)d[i].n, d[i].n_edges, d[i].edges, d[i].J);
+            const auto ek = std::make_tuple((int64_t)d[i].n, d[i].n_edges, d[i].edges, d[i].J, d[i].seed);
             auto it = explicit_of.find(ek);
             if (it == explicit_of.end()) {
                 it = explicit_of.emplace(ek, (int32_t)first_inst.size()).first;
@@ -790,8 +799,9 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     // batch's work is spread over several workgroups (members) that meet at a
     // device-scope barrier after every colour class.  Each member keeps at
     // least two 64-position chunks per wavefront of the largest class, and
-    // the members of all split units of a context use at most half of the
-    // CUs, so that they can all be resident at once next to other work.
+    // the members of all split units of all contexts of the process on the
+    // device use at most half of the CUs (a process-wide ledger), so that
+    // they can all be resident at once next to other work.
     // Splitting shortens a launch only if no unit left whole outlasts the
     // split ones, so the automatic choice splits the units far above a CU's
     // share (by work) only when all of them get at least two members, or
@@ -810,42 +820,50 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         int64_t total = 0;
         for (const auto& u : plan) total += u.work;
         const int64_t share = std::max<int64_t>(1, total / std::max(1, n_cu));
-        int budget = n_cu / 2;
-        std::vector<size_t> by_work(plan.size());
-        for (size_t i = 0; i < plan.size(); ++i) by_work[i] = i;
-        std::stable_sort(by_work.begin(), by_work.end(),
-                         [&](size_t a, size_t b) { return plan[a].work > plan[b].work; });
-        size_t n_auto = 0;
-        if (forced == 0) {
-            size_t cand = 0;
-            while (cand < by_work.size() && !plan[by_work[cand]].resident && plan[by_work[cand]].work >= 2 * share)
-                ++cand;
-            for (size_t m = std::min(cand, (size_t)(budget / 2)); m >= 1; --m) {
-                const int64_t rest = by_work.size() > m ? plan[by_work[m]].work : 0;
-                if (m == cand || plan[by_work[m - 1]].work >= 3 * rest) {
-                    n_auto = m;
-                    break;
+        // the members of every split unit of the process on this device
+        // together stay within half of the CUs (members reserved while their
+        // context lives, so that all of them can be resident at once)
+        c->split_held = g_split_ledger.reserve(c->device, n_cu / 2, [&](int avail) {
+            int budget = avail;
+            std::vector<size_t> by_work(plan.size());
+            for (size_t i = 0; i < plan.size(); ++i) by_work[i] = i;
+            std::stable_sort(by_work.begin(), by_work.end(),
+                             [&](size_t a, size_t b) { return plan[a].work > plan[b].work; });
+            size_t n_auto = 0;
+            if (forced == 0) {
+                size_t cand = 0;
+                while (cand < by_work.size() && !plan[by_work[cand]].resident && plan[by_work[cand]].work >= 2 * share)
+                    ++cand;
+                for (size_t m = std::min(cand, (size_t)(budget / 2)); m >= 1; --m) {
+                    const int64_t rest = by_work.size() > m ? plan[by_work[m]].work : 0;
+                    if (m == cand || plan[by_work[m - 1]].work >= 3 * rest) {
+                        n_auto = m;
+                        break;
+                    }
                 }
             }
-        }
-        // members per unit: with few split units many members pay, with many
-        // the per-class barriers of thinly spread members cost more than
-        // they save (16 graphs: 4 members 59 us per sweep, 8 members 73 us)
-        const int per_unit = n_auto == 0 ? 0 : std::min(budget / (int)n_auto, n_auto <= 2 ? 16 : n_auto <= 8 ? 8 : 4);
-        for (size_t r = 0; r < by_work.size(); ++r) {
-            UnitPlan& u = plan[by_work[r]];
-            if (forced == 1 || u.resident || (forced == 0 && r >= n_auto)) continue;
-            const VbGraph& g = graphs[(size_t)u.group];
-            int32_t maxcls = 0;
-            for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
-            const int64_t chunk_cap = ((maxcls + 63) / 64) / (2 * (u.threads / 64));
-            int64_t want = forced >= 2 ? forced : std::min<int64_t>({16, u.work / share, (int64_t)per_unit});
-            want = std::min<int64_t>(want, std::min<int64_t>(chunk_cap, budget));
-            if (want >= 2) {
-                u.members = (int)want;
-                budget -= (int)want;
+            // members per unit: with few split units many members pay, with many
+            // the per-class barriers of thinly spread members cost more than
+            // they save (16 graphs: 4 members 59 us per sweep, 8 members 73 us)
+            const int per_unit = n_auto == 0 ? 0 : std::min(budget / (int)n_auto, n_auto <= 2 ? 16 : n_auto <= 8 ? 8 : 4);
+            for (size_t r = 0; r < by_work.size(); ++r) {
+                UnitPlan& u = plan[by_work[r]];
+                if (forced == 1 || u.resident || (forced == 0 && r >= n_auto)) continue;
+                const VbGraph& g = graphs[(size_t)u.group];
+                int32_t maxcls = 0;
+                for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
+                const int64_t chunk_cap = ((maxcls + 63) / 64) / (2 * (u.threads / 64));
+                int64_t want = forced >= 2 ? forced : std::min<int64_t>({16, u.work / share, (int64_t)per_unit});
+                want = std::min<int64_t>(want, std::min<int64_t>(chunk_cap, budget));
+                if (want >= 2) {
+                    u.members = (int)want;
+                    budget -= (int)want;
+                }
             }
-        }
+            int used = 0;
+            for (const auto& u : plan) used += u.members > 1 ? u.members : 0;
+            return used;
+        });
     }
     std::stable_sort(plan.begin(), plan.end(), [](const UnitPlan& a, const UnitPlan& b) {
         const bool sa = a.members > 1, sb = b.members > 1;
@@ -1337,9 +1355,12 @@ sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream)
         if (c->kind == 0) {
             const int64_t cap = std::max<int64_t>(
                 1, std::min<int64_t>(4096, ((int64_t)1 << 36) / std::max<int64_t>(1, c->updates_per_sweep)));
+            // launches of near-equal length (at most two distinct lengths),
+            // so that no short launch trails a call
+            const int64_t n_launch = (n_sweeps + cap - 1) / cap;
             int64_t left = n_sweeps;
-            while (left > 0) {
-                const int64_t chunk = std::min(left, cap);
+            for (int64_t li = 0; li < n_launch; ++li) {
+                const int64_t chunk = (left + (n_launch - li) - 1) / (n_launch - li);
                 if (c->use_graph)
                     hip_check(hipGraphLaunch(vb_graph_for(c, (int32_t)chunk), s));
                 else
@@ -1467,6 +1488,22 @@ void sg_free(sg_ctx* c)
     c->sync_own();
     c->release();
     delete c;
+}
+
+sg_status sg_sk_corrupt_field(sg_ctx* c, int32_t instance, int32_t replica, int64_t i, int32_t delta)
+{
+    if (!c || c->kind != 1 || instance < 0 || instance >= c->count || replica < 0 || replica >= c->R)
+        return SG_EINVAL;
+    const SkChain& S = c->sk[(size_t)(instance * c->R + replica)];
+    if (i < 0 || i >= S.n) return SG_EINVAL;
+    return guarded([&]() {
+        hip_check(hipSetDevice(c->device));
+        c->sync_own();
+        int32_t h = 0;
+        hip_check(hipMemcpy(&h, S.H + i, 4, hipMemcpyDeviceToHost));
+        h += delta;
+        hip_check(hipMemcpy(S.H + i, &h, 4, hipMemcpyHostToDevice));
+    });
 }
 
 sg_status sg_vb_inspect(const sg_vb_desc* d, sg_vb_tables* out)

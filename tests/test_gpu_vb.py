@@ -135,7 +135,9 @@ def test_vb_batched_full_size_prefix_sampled():
     assert np.all(G[:, :, np.arange(8), np.arange(8)] == 65536)
     assert np.array_equal(G, np.transpose(G, (0, 1, 3, 2)))
     assert np.all(G[:, :, 8:, :] == 0)
-    for i in (0, 383, 767):
+    # graphs 0, 127, 255 (maximum degree 15) and graphs 2 and 10 (a vertex of
+    # degree 16 and 19: their chunks take the 8-bit count path)
+    for i in (0, 6, 31, 383, 767):
         ref = oracle_vb(descs[i], n_sw, workloads.VB_BATCHED_SWEEPS)
         assert_instance_equal(res, i, ref, spins=False, label="inst %d" % i)
     assert res["bond"].shape == (768, 2, K)

@@ -295,3 +295,49 @@ def test_sk_aligned_start():
     o = oracle.sk_run(n, J, 0.5, 1, 0, 2, 0, 0, start=oracle.START_ALIGNED)
     assert np.all(o["spins"] == 1)
     assert o["bond"][0, 0] == int(np.triu(J.astype(np.int64), 1).sum())
+
+
+def test_sk_observables_recomputed_from_configurations():
+    # Bond, overlap and Gram of the SK run against values recomputed with
+    # numpy from the configurations themselves: snapshots obtained by
+    # re-running the oracle to each grid time, the start rebuilt from the
+    # INIT stream (SK visits i = 0..N-1, so position = vertex).
+    n, T, t_max = 200, 0.5, 32
+    J = oracle.sk_couplings(n, seed=4, graph_id=3)
+    A = np.triu(J.astype(np.int64), 1)
+    full = oracle.sk_run(n, J, T, 4, 6, 2, t_max, t_max)
+    K = len(full["times"])
+    assert full["k_done"] == K
+    snaps = np.stack([oracle.sk_run(n, J, T, 4, 6, 2, int(t), t_max)["spins"] for t in full["times"]])
+    S = snaps.astype(np.int64)                     # [K][replica][n]
+    for r in range(2):
+        G = S[:, r, :] @ S[:, r, :].T
+        assert np.array_equal(G, full["gram"][r])
+        assert np.all(np.diag(G) == n)             # C(t, t) = 1
+        for k in range(K):
+            assert full["bond"][r, k] == int(S[k, r] @ A @ S[k, r])
+    for k in range(K):
+        assert full["overlap"][0, k] == int(S[k, 0] @ S[k, 1])
+    assert np.array_equal(S[-1], full["spins"].astype(np.int64))
+    for r in range(2):
+        init = np.array([oracle.init_spin(4, 6, r, i) for i in range(n)], np.int64)
+        assert np.array_equal(S[0, r], init)
+        assert full["gram"][r, 0, -1] == int(init @ S[-1, r])
+
+
+def test_sk_infinite_temperature_observables_alternate():
+    # T = inf: every move is accepted, s(t) = (-1)^t s(0), so the Gram matrix
+    # is +-N by the parity of t - t', and bond sums and overlaps are constant.
+    n = 300
+    J = oracle.sk_couplings(n, seed=2, graph_id=5)
+    o = oracle.sk_run(n, J, math.inf, 2, 1, 3, 64, 64)
+    times = o["times"]
+    for k, t in enumerate(times):
+        for l, u in enumerate(times):
+            assert np.all(o["gram"][:, k, l] == (n if (t - u) % 2 == 0 else -n))
+    assert np.all(o["bond"] == o["bond"][:, :1])
+    assert np.all(o["overlap"] == o["overlap"][:, :1])
+    s0 = oracle.sk_run(n, J, math.inf, 2, 1, 3, 0, 64)["spins"].astype(np.int64)
+    pairs = [(a, b) for a in range(3) for b in range(a + 1, 3)]
+    for p, (a, b) in enumerate(pairs):
+        assert o["overlap"][p, 0] == int(s0[a] @ s0[b])
