@@ -79,7 +79,11 @@ def _load():
         lib.orc_grid.argtypes = [i64, P]
         lib.orc_grid.restype = i32
         lib.orc_vb_run.argtypes = [i64, i64, P, P, P, f64, u64, u32, i32, i32, P, i64, i64, i32,
-                                   P, P, P, P, P, P, P]
+                                   P, P, P, P, P, P, P, i64, P, P]
+        lib.orc_window_bin.argtypes = [u64]
+        lib.orc_window_bin.restype = i32
+        lib.orc_window_tw_count.argtypes = [i64, i64]
+        lib.orc_window_tw_count.restype = i32
         lib.orc_vb_run.restype = ctypes.c_int
         lib.orc_sk_run.argtypes = [i64, P, f64, u64, u32, i32, i32, P, i64, i64, i32,
                                    P, P, P, P, P, P, P]
@@ -201,9 +205,20 @@ def _finish(o, n_rep):
     return o
 
 
+def window_bin(tau: int) -> int:
+    """Minor-third interval of time tau >= 1 (see orc_window_bin)."""
+    return int(_load().orc_window_bin(int(tau)))
+
+
+def window_tw_count(t_max: int, tw_max: int) -> int:
+    return int(_load().orc_window_tw_count(int(t_max), int(tw_max)))
+
+
 def vb_run(n, eu, ev, J, T, seed, inst, n_rep, n_sweeps, t_max, start=START_RANDOM,
-           s0=None, mode=0):
-    """One VB instance, n_rep replicas, n_sweeps sweeps (see orc_vb_run)."""
+           s0=None, mode=0, window_tw_max=None):
+    """One VB instance, n_rep replicas, n_sweeps sweeps (see orc_vb_run).  With
+    window_tw_max, also the windowed correlation sums `window` [n_rep][kw][M]
+    and their interval counts `window_count` [kw][M]."""
     eu = np.ascontiguousarray(eu, dtype=np.int32)
     ev = np.ascontiguousarray(ev, dtype=np.int32)
     J = np.ascontiguousarray(J, dtype=np.int8)
@@ -211,13 +226,25 @@ def vb_run(n, eu, ev, J, T, seed, inst, n_rep, n_sweeps, t_max, start=START_RAND
         s0 = np.ascontiguousarray(s0, dtype=np.int8).reshape(n_rep, n)
     K = len(grid(t_max))
     o = _outputs(n, n_rep, K)
+    win = cnt = None
+    tw = -1
+    if window_tw_max is not None:
+        tw = int(window_tw_max)
+        kw = window_tw_count(t_max, tw)
+        nb = window_bin(t_max) + 1
+        win = np.zeros((n_rep, kw, nb), np.int64)
+        cnt = np.zeros((kw, nb), np.int64)
     rc = _load().orc_vb_run(n, len(eu), _ptr(eu), _ptr(ev), _ptr(J), float(T), seed, inst, n_rep,
                             start, _ptr(s0), n_sweeps, t_max, mode, _ptr(o["times"]),
                             _ptr(o["bond"]), _ptr(o["overlap"]), _ptr(o["gram"]),
-                            _ptr(o["accepted"]), _ptr(o["spins"]), ctypes.byref(o["k"]))
+                            _ptr(o["accepted"]), _ptr(o["spins"]), ctypes.byref(o["k"]),
+                            tw, _ptr(win), _ptr(cnt))
     if rc != 0:
         raise ValueError("orc_vb_run rejected its arguments")
-    return _finish(o, n_rep)
+    out = _finish(o, n_rep)
+    if win is not None:
+        out["window"], out["window_count"] = win, cnt
+    return out
 
 
 def sk_run(n, J, T, seed, inst, n_rep, n_sweeps, t_max, start=START_RANDOM, s0=None,

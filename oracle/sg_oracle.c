@@ -310,6 +310,35 @@ static int is_grid_time(int64_t t)
     return t == 0 || (t > 0 && (t & (t - 1)) == 0);
 }
 
+/* Windowed correlation (the paper's estimator: the measured C(t_w + t, t_w)
+ * averaged over geometric "minor third" time intervals, ratio 2^(1/4) from
+ * one to the next; Results and discussion, and the SI section on the
+ * extrapolation to large sizes and times).  Here the intervals are taken in
+ * the absolute time tau = t_w + t: interval m holds the integer times with
+ * 2^(m/4) <= tau < 2^((m+1)/4), so m = floor(4 log2 tau) = floor(log2 tau^4),
+ * computed from the exact fourth power (tau < 2^32, so tau^4 < 2^128). */
+int32_t orc_window_bin(uint64_t tau)
+{
+    unsigned __int128 p = (unsigned __int128)tau * (unsigned __int128)tau;
+    p = p * p;
+    int32_t m = -1;
+    while (p != 0) {
+        p >>= 1;
+        ++m;
+    }
+    return m;
+}
+
+/* Number of waiting times of the windowed estimator: the grid times <= tw_max. */
+int32_t orc_window_tw_count(int64_t t_max, int64_t tw_max)
+{
+    int64_t grid[70];
+    int32_t K = orc_grid(t_max, grid), kw = 0;
+    for (int32_t k = 0; k < K; ++k)
+        if (grid[k] <= tw_max) ++kw;
+    return kw;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Viana-Bray                                                                 */
 /* ------------------------------------------------------------------------ */
@@ -322,14 +351,29 @@ static int is_grid_time(int64_t t)
  *  times[K], bond[n_rep][K], overlap[n_pairs][K] (pairs a<b in lexicographic
  *  order), gram[n_rep][K][K], accepted[n_rep], spins[n_rep][n] (vertex order,
  *  after the last sweep), k_done = number of grid times reached.
+ * Windowed correlation, when window != NULL (t_max >= 1): waiting times are
+ * the kw = orc_window_tw_count(t_max, tw_max) first grid times, intervals
+ * m = 0 .. M-1 with M = orc_window_bin(t_max) + 1; after every sweep that
+ * ends at a time tau <= t_max, for every waiting time t_w < tau,
+ *   window[r][k][m(tau)] += sum_i s_i(tau) s_i(t_w)   (replica r),
+ *   window_count[k][m(tau)] += 1,
+ * so that window / (window_count n) is C(tau, t_w) averaged over interval m.
  * Returns 0, or -1 on bad input. */
 int orc_vb_run(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const int8_t* J,
                double T, uint64_t seed, uint32_t inst, int32_t n_rep, int32_t start,
                const int8_t* s0, int64_t n_sweeps, int64_t t_max, int32_t mode,
                int64_t* times, int64_t* bond, int64_t* overlap, int64_t* gram,
-               int64_t* accepted, int8_t* spins, int32_t* k_done)
+               int64_t* accepted, int8_t* spins, int32_t* k_done,
+               int64_t tw_max, int64_t* window, int64_t* window_count)
 {
     if (n < 1 || n_rep < 1 || n_sweeps < 0 || t_max < 0) return -1;
+    if (window && (t_max < 1 || tw_max < 0 || !window_count)) return -1;
+    const int32_t kw = window ? orc_window_tw_count(t_max, tw_max) : 0;
+    const int32_t n_bins = window ? orc_window_bin((uint64_t)t_max) + 1 : 0;
+    if (window) {
+        memset(window, 0, sizeof(int64_t) * (size_t)n_rep * (size_t)kw * (size_t)n_bins);
+        memset(window_count, 0, sizeof(int64_t) * (size_t)kw * (size_t)n_bins);
+    }
     adj_t g;
     if (adj_build(&g, n, m, eu, ev, J) != 0) return -1;
     int32_t* colour = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
@@ -407,6 +451,19 @@ int orc_vb_run(int64_t n, int64_t m, const int32_t* eu, const int32_t* ev, const
                     }
                     memcpy(s, nxt, (size_t)n);
                     p = q;
+                }
+            }
+            /* windowed correlation at the time this sweep ends */
+            const int64_t tau = t + 1;
+            if (window && tau <= t_max) {
+                const int32_t bin = orc_window_bin((uint64_t)tau);
+                for (int32_t kk = 0; kk < kw; ++kk) {
+                    if (times[kk] >= tau) continue;
+                    const int8_t* sw = snaps + ((int64_t)r * K + kk) * n;
+                    int64_t O = 0;
+                    for (int64_t i = 0; i < n; ++i) O += s[i] * sw[i];
+                    window[((int64_t)r * kw + kk) * n_bins + bin] += O;
+                    if (r == 0) window_count[(int64_t)kk * n_bins + bin] += 1;
                 }
             }
         }
