@@ -237,6 +237,21 @@ sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream);
  * if an SK field check has failed since the context was created. */
 sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream);
 
+/* Variant of sg_measure for callers that cannot allocate memory (code that
+ * must not call hipMalloc, such as tight serving loops or hosts that forbid
+ * allocation after set-up).  Same observables, same values and the same
+ * statuses as sg_measure with flags = SG_MEASURE_OBS, for the arrays of `out`
+ * that are not NULL; out->spins must be NULL (SG_EINVAL otherwise).  The
+ * measurement kernels stage their results in a fixed device array of
+ * 2^20 int64 (8 MiB) that the library holds on each device until the process
+ * ends, and the results are copied straight into the caller's arrays: no
+ * device or host memory is allocated.  A context needs
+ * count R K (1 + K) + count R (R - 1) / 2 K of those entries (K = grid size);
+ * larger contexts get SG_ENOTSUP.  Waits for `stream` before returning.
+ * Calls that overlap on one device (from several host threads, with any
+ * contexts) race on the shared array and must be serialised by the caller. */
+sg_status sg_measure_noalloc(sg_ctx* c, sg_obs* out, void* stream);
+
 /* Waits for every stream the context's calls have used (and for its set-up
  * work), never for other contexts, and releases everything it owns.
  * sg_free(NULL) does nothing. */

@@ -27,8 +27,8 @@ START_RANDOM, START_ALIGNED, START_GIVEN = 0, 1, 2
 MEASURE_OBS, MEASURE_SPINS = 1, 2
 OPT_AUTOTUNE, OPT_GRAPH = 1, 2
 
-EXPORTS = ("sg_create_vb", "sg_create_sk", "sg_sweep", "sg_measure", "sg_free", "sg_strerror",
-           "sg_vb_inspect", "sg_sk_inspect", "sg_sk_corrupt_field")
+EXPORTS = ("sg_create_vb", "sg_create_sk", "sg_sweep", "sg_measure", "sg_measure_noalloc", "sg_free",
+           "sg_strerror", "sg_vb_inspect", "sg_sk_inspect", "sg_sk_corrupt_field")
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -95,6 +95,8 @@ def library() -> ctypes.CDLL:
         lib.sg_sweep.restype = ctypes.c_int32
         lib.sg_measure.argtypes = [P, ctypes.c_uint32, P, P]
         lib.sg_measure.restype = ctypes.c_int32
+        lib.sg_measure_noalloc.argtypes = [P, P, P]
+        lib.sg_measure_noalloc.restype = ctypes.c_int32
         lib.sg_free.argtypes = [P]
         lib.sg_free.restype = None
         lib.sg_strerror.argtypes = [ctypes.c_int32]
@@ -323,6 +325,27 @@ def sg_measure(ctx: Context, flags: int = MEASURE_OBS, stream=None, check: bool 
             out.append(spins[base:base + R * n].reshape(R, n))
             base += R * n
         res["spins"] = out
+    return res
+
+
+def sg_measure_noalloc(ctx: Context, stream=None, check: bool = True) -> dict:
+    """The observables of sg_measure(ctx, MEASURE_OBS) through the entry point
+    that allocates no memory (see include/sg.h); status in res["status"]."""
+    count, R, K = len(ctx.ns), ctx.R, ctx.K
+    npair = R * (R - 1) // 2
+    res = dict(times=np.zeros(K, np.int64), bond=np.zeros((count, R, K), np.int64),
+               overlap=np.zeros((count, npair, K), np.int64),
+               gram=np.zeros((count, R, K, K), np.int64), accepted=np.zeros((count, R), np.int64))
+    o = _Obs()
+    o.times, o.bond, o.gram = _p(res["times"]), _p(res["bond"]), _p(res["gram"])
+    o.accepted = _p(res["accepted"])
+    o.overlap = _p(res["overlap"]) if npair else None
+    code = library().sg_measure_noalloc(ctx.ptr, ctypes.byref(o), _stream_handle(stream))
+    res["status"] = code
+    if check:
+        _check(code, "sg_measure_noalloc")
+    res["k_done"] = o.k_done
+    res["t_done"] = o.t_done
     return res
 
 

@@ -1267,6 +1267,34 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     hip_check(hipStreamSynchronize(nullptr));
 }
 
+// Enqueues the measurement kernels of every grid time reached (kd of them)
+// on stream s: bond sums into bond[chains][K] (SK: 2 B, halved by the
+// caller), overlaps into overlap[pairs][K], Gram matrices into
+// gram[chains][K][K] (zeroed first: the kernel accumulates).
+void enqueue_obs(sg_ctx* c, int32_t kd, long long* bond, long long* overlap, long long* gram, hipStream_t s)
+{
+    const int32_t K = c->K;
+    if (c->kind == 0) {
+        hip_check(vb_bond(c->units_d, (int)c->units.size(), kd, bond, c->unit_chain_ids_d, K,
+                          std::min(1024, c->vb_threads), c->bond_lds, s));
+    } else {
+        hip_check(zero_i64(bond, (size_t)c->n_chains * K, s));
+        hip_check(sk_bond(c->sks_d, c->count, c->sk_d, c->sk_max_n, c->R, kd, K, bond, s));
+    }
+    hip_check(measure_overlap(c->mc_d, c->pairs_d, c->n_pairs, kd, K, overlap, s));
+    hip_check(zero_i64(gram, (size_t)c->n_chains * K * K, s));
+    hip_check(measure_gram(c->mc_d, c->n_chains, kd, K, c->max_words, gram, s));
+}
+
+// Status of a measurement from the context's error word.
+sg_status status_of_flag(int err_flag)
+{
+    // a sweep pipeline stalled, a split unit's barrier timed out, or the VB
+    // sweep kernel found its dynamic LDS away from offset 0
+    if (err_flag & 14) return SG_EDEVICE;
+    return (err_flag & 1) ? SG_EPARITY : SG_OK;
+}
+
 template <class F>
 sg_status guarded(F&& f)
 {
@@ -1400,17 +1428,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
         out->k_done = kd;
         out->t_done = c->t_done;
         if (flags & SG_MEASURE_OBS) {
-            if (c->kind == 0) {
-                hip_check(vb_bond(c->units_d, (int)c->units.size(), kd, c->bond_d, c->unit_chain_ids_d, K,
-                                  std::min(1024, c->vb_threads), c->bond_lds, s));
-            } else {
-                // accumulates 2 B per (chain, grid time); halved below
-                hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * K, s));
-                hip_check(sk_bond(c->sks_d, c->count, c->sk_d, c->sk_max_n, R, kd, K, c->bond_d, s));
-            }
-            hip_check(measure_overlap(c->mc_d, c->pairs_d, c->n_pairs, kd, K, c->overlap_d, s));
-            hip_check(zero_i64(c->gram_d, (size_t)c->n_chains * K * K, s));
-            hip_check(measure_gram(c->mc_d, c->n_chains, kd, K, c->max_words, c->gram_d, s));
+            enqueue_obs(c, kd, c->bond_d, c->overlap_d, c->gram_d, s);
             std::vector<long long> bond((size_t)c->n_chains * K), ovl((size_t)std::max(1, c->n_pairs) * K),
                 gram((size_t)c->n_chains * K * K);
             std::vector<unsigned long long> acc((size_t)c->n_chains);
@@ -1475,10 +1493,55 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
         }
     });
     if (st != SG_OK) return st;
-    // a sweep pipeline stalled, a split unit's barrier timed out, or the VB
-    // sweep kernel found its dynamic LDS away from offset 0
-    if (err_flag & 14) return SG_EDEVICE;
-    return (err_flag & 1) ? SG_EPARITY : SG_OK;
+    return status_of_flag(err_flag);
+}
+
+sg_status sg_measure_noalloc(sg_ctx* c, sg_obs* out, void* stream)
+{
+    if (!c || !out) return SG_EINVAL;
+    if (out->spins) return SG_EINVAL;   // spins need host staging: sg_measure only
+    const size_t K = (size_t)c->K;
+    const size_t n_bond = (size_t)c->n_chains * K, n_ovl = (size_t)c->n_pairs * K;
+    const size_t n_gram = (size_t)c->n_chains * K * K;
+    if (n_bond + n_ovl + n_gram > kMeasureScratchElems) return SG_ENOTSUP;
+    int err_flag = 0;
+    sg_status st = guarded([&]() {
+        hip_check(hipSetDevice(c->device));
+        long long* scr = nullptr;
+        hip_check(measure_scratch(&scr));   // this device's copy of the fixed array
+        // (the stream is not recorded for sg_free: this call waits for it)
+        hipStream_t s = (hipStream_t)stream;
+        const int32_t kd = c->k_done();
+        out->count = c->count;
+        out->n_replicas = c->R;
+        out->k_cap = c->K;
+        out->k_done = kd;
+        out->t_done = c->t_done;
+        long long* bond = scr;
+        long long* ovl = scr + n_bond;
+        long long* gram = ovl + n_ovl;
+        enqueue_obs(c, kd, bond, ovl, gram, s);
+        // straight into the caller's arrays (int64 on both sides)
+        if (out->bond) hip_check(hipMemcpyAsync(out->bond, bond, n_bond * 8, hipMemcpyDeviceToHost, s));
+        if (out->overlap && n_ovl)
+            hip_check(hipMemcpyAsync(out->overlap, ovl, n_ovl * 8, hipMemcpyDeviceToHost, s));
+        if (out->gram) hip_check(hipMemcpyAsync(out->gram, gram, n_gram * 8, hipMemcpyDeviceToHost, s));
+        if (out->accepted)
+            hip_check(hipMemcpyAsync(out->accepted, c->acc_d, (size_t)c->n_chains * 8, hipMemcpyDeviceToHost, s));
+        hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+        hip_check(hipStreamSynchronize(s));
+        if (out->times)
+            for (size_t k = 0; k < K; ++k) out->times[k] = c->times[k];
+        // entries of grid times not reached hold the previous call's values
+        if (out->bond)
+            for (size_t i = 0; i < n_bond; ++i)
+                out->bond[i] = (int64_t)(i % K) < kd ? out->bond[i] / (c->kind == 1 ? 2 : 1) : 0;
+        if (out->overlap)
+            for (size_t i = 0; i < n_ovl; ++i)
+                if ((int64_t)(i % K) >= kd) out->overlap[i] = 0;
+    });
+    if (st != SG_OK) return st;
+    return status_of_flag(err_flag);
 }
 
 void sg_free(sg_ctx* c)

@@ -24,6 +24,7 @@ constexpr int kVbXMax = 64;        // threshold table length (max degree 63)
 constexpr int kMaxGrid = 32;       // grid times {0} U {2^k <= t_max}, t_max < 2^31
 constexpr int kSkTile = 64;        // SK decision block (one wavefront)
 constexpr int kSkThrLds = 1024;    // SK threshold entries cached in LDS
+constexpr size_t kMeasureScratchElems = (size_t)1 << 20;   // int64 staging of sg_measure_noalloc (8 MiB)
 
 // Packed spins of a VB work unit with `rpad` (1, 2, 4 or 8) chain slots,
 // "sliced" so that one 32-bit word holds P = 32 / rpad consecutive positions
@@ -154,5 +155,8 @@ hipError_t measure_overlap(const MeasureChain* chains, const int32_t* pairs, int
 hipError_t measure_gram(const MeasureChain* chains, int n_chains, int k_done, int k_cap,
                         int max_words, long long* out, hipStream_t s);
 hipError_t zero_i64(long long* p, size_t n, hipStream_t s);
+// Device address of the fixed staging array (kMeasureScratchElems int64) on
+// the current device; looked up once per device.
+hipError_t measure_scratch(long long** ptr);
 
 }  // namespace sg

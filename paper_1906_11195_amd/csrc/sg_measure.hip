@@ -12,6 +12,15 @@
 //    pass over the unit's adjacency per snapshot time.
 #include "sg_internal.h"
 
+#include <mutex>
+
+// Staging of sg_measure_noalloc (bond sums, overlaps, Gram matrices before
+// they are copied to the caller's host arrays): a fixed device array instead
+// of memory allocated by the library.  Each device holds its own copy until
+// the process ends.  In host code the name stands for a host-side shadow, so
+// the kernels get the device address from measure_scratch() instead.
+static __device__ __align__(256) long long scratch[sg::kMeasureScratchElems];
+
 namespace sg {
 namespace {
 
@@ -157,6 +166,27 @@ hipError_t zero_i64(long long* p, size_t n, hipStream_t s)
     const int blocks = (int)std::min<size_t>(1024, (n + 255) / 256);
     hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
+}
+
+hipError_t measure_scratch(long long** ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static long long* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        // once per device, with that device current: its copy's address
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<long long*>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t measure_gram(const MeasureChain* chains, int n_chains, int k_done, int k_cap,
