@@ -179,12 +179,27 @@ typedef struct sg_opts {
     int32_t threads_per_unit;
     uint32_t flags;
     int32_t split_members;
+    int64_t window_tw_max;
 } sg_opts;
 
-/* sg_opts.flags (VB contexts; no effect on any result) */
+/* sg_opts.flags (VB contexts; AUTOTUNE and GRAPH have no effect on any result) */
 #define SG_OPT_AUTOTUNE 1u   /* time candidate workgroup sizes per launch group at create
                                 (on a saved copy of the state, restored afterwards) */
 #define SG_OPT_GRAPH 2u      /* replay each sweep chunk as a captured hipGraph */
+/* SG_OPT_WINDOW: also measure the windowed correlation, the paper's estimator
+ * of C (Results and discussion: each measurement averages the time interval
+ * [t / 2^(1/4), t]; SI, extrapolation to large sizes and times: C(t_w + t,
+ * t_w) is averaged over "minor third" intervals of t_w + t whose bounds grow
+ * by 2^(1/4)).  Reading used here: interval m holds the times tau = t_w + t
+ * with 2^(m/4) <= tau < 2^((m+1)/4), i.e. m = floor(log2 tau^4) (exact
+ * integer arithmetic), for m = 0 .. n_bins - 1, n_bins = m(t_max) + 1.  The
+ * waiting times are the first kw grid times, those <= window_tw_max
+ * (>= 0).  After every sweep ending at a time tau <= t_max, every chain adds,
+ * for each waiting time t_w < tau, the overlap sum_i s_i(tau) s_i(t_w) to
+ * its sum for (t_w, m(tau)); window_count[k][m] counts the terms, so that
+ * window / (window_count n) is C(tau, t_w) averaged over interval m.  Needs
+ * t_max >= 1; VB contexts only (SG_ENOTSUP for SK). */
+#define SG_OPT_WINDOW 4u
 
 #define SG_MEASURE_OBS 1u    /* times, bond, overlap, gram, accepted */
 #define SG_MEASURE_SPINS 2u  /* current spins, vertex order */
@@ -213,6 +228,10 @@ typedef struct sg_obs {
     int64_t* gram;      /* [count][n_replicas][k_cap][k_cap] */
     int64_t* accepted;  /* [count][n_replicas] */
     int8_t* spins;      /* [sum_i n_replicas n_i] */
+    int32_t kw;         /* waiting times of the windowed correlation (0: not measured) */
+    int32_t n_bins;     /* its intervals */
+    int64_t* window;    /* [count][n_replicas][kw][n_bins] overlap sums (SG_OPT_WINDOW) */
+    int64_t* window_count;   /* [kw][n_bins] number of terms of each sum */
 } sg_obs;
 
 /* Creates a context holding `count` VB instances on the current HIP device,

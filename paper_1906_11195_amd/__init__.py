@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libsgmi.so")
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE, SG_ESTATE, SG_EPARITY, SG_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 START_RANDOM, START_ALIGNED, START_GIVEN = 0, 1, 2
 MEASURE_OBS, MEASURE_SPINS = 1, 2
-OPT_AUTOTUNE, OPT_GRAPH = 1, 2
+OPT_AUTOTUNE, OPT_GRAPH, OPT_WINDOW = 1, 2, 4
 
 EXPORTS = ("sg_create_vb", "sg_create_sk", "sg_sweep", "sg_measure", "sg_measure_noalloc", "sg_free",
            "sg_strerror", "sg_vb_inspect", "sg_sk_inspect", "sg_sk_corrupt_field")
@@ -54,14 +54,16 @@ class _Opts(ctypes.Structure):
     _fields_ = [("t_max", ctypes.c_int64), ("alloc", _ALLOC_FN), ("free", _FREE_FN),
                 ("user", ctypes.c_void_p), ("chains_per_unit", ctypes.c_int32),
                 ("threads_per_unit", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("split_members", ctypes.c_int32)]
+                ("split_members", ctypes.c_int32), ("window_tw_max", ctypes.c_int64)]
 
 
 class _Obs(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("n_replicas", ctypes.c_int32),
                 ("k_cap", ctypes.c_int32), ("k_done", ctypes.c_int32), ("t_done", ctypes.c_int64),
                 ("times", ctypes.c_void_p), ("bond", ctypes.c_void_p), ("overlap", ctypes.c_void_p),
-                ("gram", ctypes.c_void_p), ("accepted", ctypes.c_void_p), ("spins", ctypes.c_void_p)]
+                ("gram", ctypes.c_void_p), ("accepted", ctypes.c_void_p), ("spins", ctypes.c_void_p),
+                ("kw", ctypes.c_int32), ("n_bins", ctypes.c_int32), ("window", ctypes.c_void_p),
+                ("window_count", ctypes.c_void_p)]
 
 
 class _VbTables(ctypes.Structure):
@@ -216,9 +218,11 @@ _ALLOC_CB = _ALLOC_FN(_torch_alloc)
 _FREE_CB = _FREE_FN(_torch_free)
 
 
-def _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags=0, split_members=0):
+def _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags=0, split_members=0,
+          window_tw_max=0):
     o = _Opts()
     o.t_max = int(t_max)
+    o.window_tw_max = int(window_tw_max)
     o.chains_per_unit = int(chains_per_unit)
     o.threads_per_unit = int(threads_per_unit)
     o.flags = int(flags)
@@ -245,12 +249,14 @@ def _stream_handle(stream):
 class Context:
     """Owning handle of an sg_ctx."""
 
-    def __init__(self, ptr, kind, ns, R, K):
+    def __init__(self, ptr, kind, ns, R, K, kw=0, n_bins=0):
         self.ptr = ptr
         self.kind = kind
         self.ns = list(ns)
         self.R = R
         self.K = K
+        self.kw = kw            # windowed correlation: waiting times, intervals
+        self.n_bins = n_bins
 
     def __del__(self):
         if getattr(self, "ptr", None):
@@ -271,15 +277,24 @@ def _grid_len(t_max):
 
 def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
                  threads_per_unit: int = 0, torch_alloc: bool = True, autotune: bool = False,
-                 graph: bool = False, split_members: int = 0) -> Context:
+                 graph: bool = False, split_members: int = 0,
+                 window_tw_max: Optional[int] = None) -> Context:
+    """window_tw_max: measure the windowed correlation with the grid times
+    <= window_tw_max as waiting times (SG_OPT_WINDOW)."""
     keep = []
     arr = (_VbDesc * len(descs))(*[_vb_struct(d, keep) for d in descs])
     flags = (OPT_AUTOTUNE if autotune else 0) | (OPT_GRAPH if graph else 0)
-    o = _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags, split_members)
+    kw = n_bins = 0
+    if window_tw_max is not None:
+        flags |= OPT_WINDOW
+        kw = _grid_len(min(int(window_tw_max), int(t_max)))   # grid times <= window_tw_max
+        n_bins = (int(t_max) ** 4).bit_length()                # intervals of 1 .. t_max
+    o = _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags, split_members,
+              window_tw_max if window_tw_max is not None else 0)
     out = ctypes.c_void_p()
     _check(library().sg_create_vb(ctypes.byref(arr), len(descs), ctypes.byref(o), ctypes.byref(out)),
            "sg_create_vb")
-    return Context(out, "vb", [d.n for d in descs], descs[0].n_replicas, _grid_len(t_max))
+    return Context(out, "vb", [d.n for d in descs], descs[0].n_replicas, _grid_len(t_max), kw, n_bins)
 
 
 def sg_create_sk(descs: Sequence[SkDesc], t_max: int, threads_per_unit: int = 0,
@@ -309,6 +324,10 @@ def sg_measure(ctx: Context, flags: int = MEASURE_OBS, stream=None, check: bool 
         o.times, o.bond, o.gram = _p(res["times"]), _p(res["bond"]), _p(res["gram"])
         o.accepted = _p(res["accepted"])
         o.overlap = _p(res["overlap"]) if npair else None
+    if ctx.kw and flags & MEASURE_OBS:
+        res["window"] = np.zeros((count, R, ctx.kw, ctx.n_bins), np.int64)
+        res["window_count"] = np.zeros((ctx.kw, ctx.n_bins), np.int64)
+        o.window, o.window_count = _p(res["window"]), _p(res["window_count"])
     spins = None
     if flags & MEASURE_SPINS:
         spins = np.zeros(R * sum(ctx.ns), np.int8)
@@ -340,6 +359,10 @@ def sg_measure_noalloc(ctx: Context, stream=None, check: bool = True) -> dict:
     o.times, o.bond, o.gram = _p(res["times"]), _p(res["bond"]), _p(res["gram"])
     o.accepted = _p(res["accepted"])
     o.overlap = _p(res["overlap"]) if npair else None
+    if ctx.kw:
+        res["window"] = np.zeros((count, R, ctx.kw, ctx.n_bins), np.int64)
+        res["window_count"] = np.zeros((ctx.kw, ctx.n_bins), np.int64)
+        o.window, o.window_count = _p(res["window"]), _p(res["window_count"])
     code = library().sg_measure_noalloc(ctx.ptr, ctypes.byref(o), _stream_handle(stream))
     res["status"] = code
     if check:

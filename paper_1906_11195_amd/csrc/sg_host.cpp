@@ -377,6 +377,9 @@ struct sg_ctx {
     }
     int32_t count = 0, R = 0, K = 0, n_chains = 0;
     int64_t t_max = 0, t_done = 0;
+    // windowed correlation (VB): waiting times, intervals, sums per chain
+    int32_t kw = 0, n_bins = 0;
+    long long* win_d = nullptr;           // [n_chains][kw][n_bins]
     std::vector<int64_t> times;
     std::vector<int64_t> n_of;            // spins per instance
     // VB
@@ -497,6 +500,13 @@ void setup_common(sg_ctx* c, const sg_opts* o)
             (o->threads_per_unit < 64 || o->threads_per_unit > 1024 || o->threads_per_unit % 64))
             fail(SG_EINVAL);
         if (o->chains_per_unit < 0 || o->chains_per_unit > kVbMaxChains) fail(SG_EINVAL);
+        if (o->flags & SG_OPT_WINDOW) {
+            if (c->t_max < 1 || o->window_tw_max < 0) fail(SG_EINVAL);
+            c->kw = 0;
+            for (int64_t t : c->times)
+                if (t <= o->window_tw_max) ++c->kw;
+            c->n_bins = vb_window_bin((uint64_t)c->t_max) + 1;
+        }
     }
     int dev_count = 0;
     if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count == 0) fail(SG_EDEVICE);
@@ -900,6 +910,14 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         }
         c->max_words = std::max(c->max_words, (int)wn);
     }
+    std::vector<size_t> off_wsnap(plan.size(), 0);
+    if (c->kw > 0)
+        for (size_t u = 0; u < plan.size(); ++u) {
+            const int64_t n = graphs[(size_t)plan[u].group].n;
+            off_wsnap[u] = A.take((size_t)VbLayout(plan[u].rpad).words(n) * 4 * (size_t)c->kw);
+        }
+    const size_t win_per_chain = (size_t)c->kw * (size_t)c->n_bins;
+    const size_t off_win = A.take(std::max<size_t>(1, (size_t)c->n_chains * win_per_chain) * 8);
     const size_t off_units = A.take((size_t)n_entries * sizeof(VbUnit));
     const size_t off_ids = A.take((size_t)n_entries * kVbMaxChains * 4);
     const size_t off_bars = A.take((size_t)std::max(1, n_split) * 8);
@@ -966,6 +984,9 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         U.rpad = plan[u].rpad;
         U.state_words = (int32_t)VbLayout(U.rpad).words(g.n);
         U.words_n = (int32_t)((g.n + 31) / 32);
+        U.kw = c->kw;
+        U.n_bins = c->n_bins;
+        U.wsnap = c->kw > 0 ? c->at<uint32_t>(off_wsnap[u]) : nullptr;
         for (int32_t k = 0; k < U.nch; ++k) {
             const int32_t ch = plan[u].chains[(size_t)k];
             const int32_t i = ch / c->R, r = ch % c->R;
@@ -976,6 +997,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
             U.rep[k] = (uint32_t)r;
             U.init_mode[k] = d[i].start;
             U.given[k] = d[i].start == SG_START_GIVEN ? c->at<uint32_t>(off_given[(size_t)ch]) : nullptr;
+            U.win[k] = c->kw > 0 ? c->at<long long>(off_win) + (size_t)ch * win_per_chain : nullptr;
             for (int32_t x = 0; x < kVbXMax; ++x) {
                 const uint64_t th = x == 0 ? (uint64_t)1 << 32 : threshold(d[i].T, 1.0, x);
                 U.thr_hi[k][x] = (uint32_t)(th >> 16);
@@ -1038,6 +1060,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     if (!pairs.empty())
         hip_check(hipMemcpy(c->pairs_d, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
     c->t_dev = c->at<int64_t>(off_t);
+    c->win_d = c->at<long long>(off_win);
+    if (c->kw > 0) hip_check(zero_i64(c->win_d, (size_t)c->n_chains * win_per_chain, nullptr));
     hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
     hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
     hip_check(zero_i64((long long*)c->t_dev, 2, nullptr));
@@ -1070,6 +1094,7 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
         if ((d[i].recompute_period ? d[i].recompute_period : 64) != c->period) fail(SG_EINVAL);
     }
     setup_common(c, o);
+    if (c->kw > 0) fail(SG_ENOTSUP);   // the windowed correlation is measured for VB only
     c->n_chains = count * c->R;
     c->n_of.resize((size_t)count);
 
@@ -1286,6 +1311,47 @@ void enqueue_obs(sg_ctx* c, int32_t kd, long long* bond, long long* overlap, lon
     hip_check(measure_gram(c->mc_d, c->n_chains, kd, K, c->max_words, gram, s));
 }
 
+// Number of terms of each windowed sum after the sweeps done so far: the
+// times tau = 1 .. min(t_done, t_max) of interval m that exceed the waiting
+// time times[k].  m(tau) does not decrease with tau, so interval m is the
+// range [first(m), first(m + 1)), first(m) = the smallest tau with m(tau) >=
+// m (a binary search; tau < 2^32).
+void window_counts(const sg_ctx* c, int64_t* out)
+{
+    const int64_t T = std::min(c->t_done, c->t_max);
+    int64_t first[kWindowBinsMax + 1];   // (no allocation: sg_measure_noalloc uses this too)
+    for (int32_t m = 0; m <= c->n_bins; ++m) {
+        uint64_t lo = 1, hi = 0xffffffffull;   // m(hi) = 127 >= m
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (vb_window_bin(mid) >= m) hi = mid;
+            else lo = mid + 1;
+        }
+        first[(size_t)m] = (int64_t)lo;
+    }
+    for (int32_t k = 0; k < c->kw; ++k)
+        for (int32_t m = 0; m < c->n_bins; ++m) {
+            const int64_t a = std::max(first[(size_t)m], c->times[(size_t)k] + 1);
+            const int64_t b = std::min(first[(size_t)m + 1] - 1, T);
+            out[(size_t)k * c->n_bins + m] = b >= a ? b - a + 1 : 0;
+        }
+}
+
+static_assert(kWindowBinsMax >= 125, "m(t_max) + 1 <= 125 for t_max < 2^31");
+
+// Copies the windowed sums (sg_obs.window, caller's host array, on stream s)
+// and fills the counts; the caller synchronises s.
+void window_out(sg_ctx* c, sg_obs* out, hipStream_t s)
+{
+    out->kw = c->kw;
+    out->n_bins = c->n_bins;
+    if (c->kw == 0) return;
+    if (out->window)
+        hip_check(hipMemcpyAsync(out->window, c->win_d, (size_t)c->n_chains * c->kw * c->n_bins * 8,
+                                 hipMemcpyDeviceToHost, s));
+    if (out->window_count) window_counts(c, out->window_count);
+}
+
 // Status of a measurement from the context's error word.
 sg_status status_of_flag(int err_flag)
 {
@@ -1438,6 +1504,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
             hip_check(hipMemcpyAsync(gram.data(), c->gram_d, gram.size() * 8, hipMemcpyDeviceToHost, s));
             hip_check(hipMemcpyAsync(acc.data(), c->acc_d, acc.size() * 8, hipMemcpyDeviceToHost, s));
             hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+            window_out(c, out, s);
             hip_check(hipStreamSynchronize(s));
             if (out->times)
                 for (int32_t k = 0; k < K; ++k) out->times[k] = c->times[(size_t)k];
@@ -1529,6 +1596,7 @@ sg_status sg_measure_noalloc(sg_ctx* c, sg_obs* out, void* stream)
         if (out->accepted)
             hip_check(hipMemcpyAsync(out->accepted, c->acc_d, (size_t)c->n_chains * 8, hipMemcpyDeviceToHost, s));
         hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+        window_out(c, out, s);
         hip_check(hipStreamSynchronize(s));
         if (out->times)
             for (size_t k = 0; k < K; ++k) out->times[k] = c->times[k];

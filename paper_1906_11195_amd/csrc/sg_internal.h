@@ -24,6 +24,7 @@ constexpr int kVbXMax = 64;        // threshold table length (max degree 63)
 constexpr int kMaxGrid = 32;       // grid times {0} U {2^k <= t_max}, t_max < 2^31
 constexpr int kSkTile = 64;        // SK decision block (one wavefront)
 constexpr int kSkThrLds = 1024;    // SK threshold entries cached in LDS
+constexpr int kWindowBinsMax = 128;  // minor-third intervals of times below 2^32
 constexpr size_t kMeasureScratchElems = (size_t)1 << 20;   // int64 staging of sg_measure_noalloc (8 MiB)
 
 // Packed spins of a VB work unit with `rpad` (1, 2, 4 or 8) chain slots,
@@ -77,7 +78,29 @@ struct VbUnit {
     int32_t member;
     uint32_t* bar;
     int* err;                  // bit 2: a barrier wait timed out; bit 3: dynamic LDS not at offset 0
+    // Windowed correlation (kw > 0): the spin words at the first kw grid
+    // times (the waiting times) in the VbLayout packing, and per chain the
+    // sums of the overlap with each of them over the minor-third interval of
+    // the time each sweep ends at (see vb_window_bin).
+    uint32_t* wsnap;           // [kw][state_words]
+    long long* win[kVbMaxChains];   // per chain: [kw][n_bins]
+    int32_t kw;
+    int32_t n_bins;
 };
+
+// Minor-third interval of time tau >= 1: m = floor(4 log2 tau) =
+// floor(log2 tau^4), from the exact 128-bit fourth power (tau < 2^32).
+__host__ __device__ __forceinline__ int32_t vb_window_bin(uint64_t tau)
+{
+    const uint64_t a = tau * tau;   // < 2^64
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint64_t hi = __umul64hi(a, a);
+#else
+    const uint64_t hi = (uint64_t)(((unsigned __int128)a * a) >> 64);
+#endif
+    const uint64_t lo = a * a;
+    return hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
+}
 
 // One SK chain (a replica of an instance).
 struct SkChain {

@@ -71,6 +71,7 @@ struct VbLds {
     int32_t* flag;                // [4]: split units' abort flag
     int32_t* cls;                 // [kMaxCls + 1] first position of each colour class
     uint32_t* ri;                 // [8][2]: replica, instance of each chain
+    uint32_t* wacc;               // [kMaxGrid][8]: window overlap counts of a sweep
     uint4* xch;                   // [waves][64] Philox blocks of a batch of chunks
     int32_t* area;                // resident adjacency: row starts, then entries
 };
@@ -91,7 +92,8 @@ __device__ __forceinline__ VbLds vb_carve(uint32_t* smem, uint32_t smem_lds, int
     L.flag = (int32_t*)(L.accs + kVbMaxChains);
     L.cls = L.flag + 4;
     L.ri = (uint32_t*)(L.cls + kMaxCls + 4);
-    L.xch = (uint4*)(L.ri + 2 * kVbMaxChains);
+    L.wacc = L.ri + 2 * kVbMaxChains;
+    L.xch = (uint4*)(L.wacc + kMaxGrid * kVbMaxChains);
     L.area = (int32_t*)(L.xch + (nthr >> 6) * 64);
     return L;
 }
@@ -471,6 +473,70 @@ __device__ void vb_snapshot(const VbUnit* __restrict__ up, const uint32_t* __res
     }
 }
 
+// Windowed correlation (the paper's estimator: C(t_w + t, t_w) averaged over
+// minor-third intervals of t_w + t, ratio 2^(1/4); Results and discussion,
+// and the SI section on the extrapolation to large sizes and times), at the
+// end of the sweep that ends at time tau <= t_max: for every stored waiting
+// time t_w < tau and every chain, the overlap sum_i s_i(tau) s_i(t_w) =
+// n - 2 popcount(s(tau) xor s(t_w)) over the chain's fields, added to the
+// chain's sum for the interval of tau.  The spin words at the waiting times
+// are stored in the same sliced packing as the LDS words, so one XOR and a
+// masked popcount per word and chain count every chain.  Each thread counts
+// (and, at the waiting times, stores) the words w = tid + member * threads
+// (mod members * threads): the members of a split unit count disjoint words
+// and no thread reads another's stores.
+template <int RPAD>
+__device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ up, uint32_t sp_off,
+                                                   uint32_t acc_off, int64_t tau, int32_t k_store)
+{
+    using S = Sl<RPAD>;
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
+    const lds_u32* sp = (const lds_u32*)(size_t)sp_off;
+    lds_u32* wacc = (lds_u32*)(size_t)acc_off;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int32_t sw = up->state_words, nch = up->nch;
+    // waiting times before tau: t_w = 0, and t_w = 2^(k-1) < tau for k >= 1
+    const int32_t kv = min(up->kw, tau >= 2 ? 2 + (63 - __clzll((unsigned long long)(tau - 1))) : 1);
+    const int32_t stride = nthr * up->members;
+    const int32_t w0 = tid + up->member * nthr;
+    SG_G uint32_t* ws = gl(up->wsnap);
+    for (int i = tid; i < kv * RPAD; i += nthr) wacc[i] = 0u;
+    __syncthreads();
+    for (int32_t k = 0; k < kv; ++k) {
+        uint32_t cnt[RPAD];
+#pragma unroll
+        for (int c = 0; c < RPAD; ++c) cnt[c] = 0u;
+        const SG_G uint32_t* wk = ws + (int64_t)k * sw;
+        for (int32_t w = w0; w < sw; w += stride) {
+            const uint32_t d = sp[w] ^ wk[w];
+#pragma unroll
+            for (int c = 0; c < RPAD; ++c)
+                if (c < nch)
+                    cnt[c] += (uint32_t)__popc(d & (S::P == 32 ? 0xffffffffu : (((1u << (S::P & 31)) - 1u) << (c * S::P))));
+        }
+#pragma unroll
+        for (int c = 0; c < RPAD; ++c) {
+            if (c < nch) {
+                uint32_t v = cnt[c];
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+                if ((tid & 63) == 0 && v) atomicAdd((uint32_t*)&wacc[k * RPAD + c], v);
+            }
+        }
+    }
+    if (k_store >= 0) {
+        SG_G uint32_t* dst = ws + (int64_t)k_store * sw;
+        for (int32_t w = w0; w < sw; w += stride) dst[w] = sp[w];
+    }
+    __syncthreads();
+    const int32_t bin = vb_window_bin((uint64_t)tau);
+    for (int i = tid; i < kv * nch; i += nthr) {
+        const int32_t k = i / nch, c = i - k * nch;
+        const long long o = (up->member == 0 ? (long long)up->n : 0ll) - 2ll * (long long)wacc[k * RPAD + c];
+        atomicAdd((unsigned long long*)(up->win[c] + (int64_t)k * up->n_bins + bin), (unsigned long long)o);
+    }
+}
+
 template <int RPAD, bool SPLIT, class PR, class PE, class PC>
 __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
                         int32_t nsw, int64_t t_max, int lane, int wave, int W);
@@ -627,8 +693,15 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
 #pragma unroll
         for (int c = 0; c < RPAD; ++c) acc[c] = 0;
         const int64_t tn = t0 + s + 1;
-        if (tn <= t_max && (tn & (tn - 1)) == 0) {
-            if (!SPLIT || up->member == 0) vb_snapshot<RPAD>(up, L.sp, 1 + (63 - __clzll((unsigned long long)tn)));
+        const bool grid = tn <= t_max && (tn & (tn - 1)) == 0;
+        const int32_t kn = grid ? 1 + (63 - __clzll((unsigned long long)tn)) : -1;
+        if (grid) {
+            if (!SPLIT || up->member == 0) vb_snapshot<RPAD>(up, L.sp, kn);
+            __syncthreads();
+        }
+        if (up->kw > 0 && tn <= t_max) {
+            vb_window<RPAD>(up, L.sp_lds, L.sp_lds + (uint32_t)((const char*)L.wacc - (const char*)L.sp), tn,
+                            kn < up->kw ? kn : -1);
             __syncthreads();
         }
     }
@@ -718,6 +791,7 @@ __global__ void __launch_bounds__(1024) vb_init_kernel(const VbUnit* __restrict_
             word |= f << (c * lay.P);
         }
         up->state[w] = word;
+        if (up->kw > 0) up->wsnap[w] = word;   // the waiting time t_w = 0
     }
 }
 
@@ -733,7 +807,7 @@ size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads)
     const size_t sw = (size_t)VbLayout(rpad).words(n);
     const size_t waves = (size_t)threads / 64;
     return ((sw + 3) & ~(size_t)3) * 4 + (size_t)kVbMaxChains * kTab * 4 + kVbMaxChains * 8 + 16 +
-           (kMaxCls + 4) * 4 + kVbMaxChains * 8 + waves * 64 * 16;
+           (kMaxCls + 4) * 4 + kVbMaxChains * 8 + (size_t)kMaxGrid * kVbMaxChains * 4 + waves * 64 * 16;
 }
 
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStream_t s)
