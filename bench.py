@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -41,21 +43,40 @@ def log(msg):
 
 
 def vb_bytes_per_sweep(descs, R, chains_per_unit):
-    """Algorithmic HBM bytes of one VB sweep: every work unit streams its
-    graph once (row starts 4 (N+1) B + entries 4 x 2M B); the spins stay in
-    LDS.  Units hold up to `chains_per_unit` chains of one graph."""
-    from paper_1906_11195_amd.workloads import VbDesc  # noqa: F401
+    """Algorithmic bytes of one VB sweep, by the scope table's model: per
+    chain-update (c w / 8 + o) / r + 1/4 B -- every work unit (r chains of one
+    graph) streams the graph once (row starts o = 4 B per vertex, entries of
+    w = 32 bits, c per vertex on average), and each chain-update reads and
+    writes its own spin bit-packed (1/4 B).  In this design the spins never
+    leave LDS during a launch, so the own-spin quarter byte is LDS traffic and
+    the HBM counters see only the graph stream.  Units hold up to
+    `chains_per_unit` chains of one graph."""
     graphs = {}
     for d in descs:
-        key = (d.n, d.c, d.seed, d.graph_id)
-        graphs.setdefault(key, [d.n, 0])
-        graphs[key][1] += R
-    total = 0
-    for (n, c, _, _), (_, chains) in graphs.items():
-        m = math.floor(c * n / 2)
+        key = (d.n, d.c, d.seed, d.graph_id, None if d.edges is None else id(d.edges))
+        m = math.floor(d.c * d.n / 2) if d.edges is None else len(d.J)
+        graphs.setdefault(key, [d.n, m, 0])
+        graphs[key][2] += R
+    total = 0.0
+    for n, m, chains in graphs.values():
         units = math.ceil(chains / chains_per_unit)
-        total += units * (4 * (n + 1) + 8 * m)
+        total += units * (4 * (n + 1) + 8 * m) + chains * n / 4.0
     return total
+
+
+def vb_chains_per_unit(n, R):
+    """Chains per work unit the library packs for one graph with R chains
+    when LDS is the limit (the planner's rule: R chains in R-slot words if
+    they fit in 159 KiB with up to 16 wavefronts, else fewer)."""
+    per = R
+    while per > 1:
+        rpad = 1 if per <= 1 else 2 if per <= 2 else 4 if per <= 4 else 8
+        sw = -(-n // (32 // rpad))
+        lds = ((sw + 3) & ~3) * 4 + 8 * 128 * 4 + 64 + 16 + 68 * 4 + 64 + 32 * 8 * 4 + 16 * 1024
+        if lds <= 160 * 1024 - 1024:
+            break
+        per -= 1
+    return per
 
 
 def percentile(xs, q):
@@ -70,7 +91,7 @@ def percentile(xs, q):
 
 PROFILE_VB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                           "vb_sweep_kernel_vb_batched_n65536.md")
-VB_KERNEL_SOURCES = ("sg_vb.hip", "sg_internal.h", "sg_philox.h")
+VB_KERNEL_SOURCES = ("sg_vb.hip", "sg_vb_unit.h", "sg_philox.h")
 
 
 def vb_kernel_digest() -> str:
@@ -239,6 +260,42 @@ def run_sk(args, torch, sg, workloads):
                           "mfma_frac": round(mfma / MFMA_INT8_PEAK_OPS, 6)})
 
 
+def run_sk_gauss(args, torch, sg, workloads):
+    """SK with Gaussian couplings (Eq. 1, variance 1/N, float32 given by the
+    input module): 64 samples x 2 replicas, N = 4096, T = 0.5, fields in
+    double, recomputed every 64 sweeps; timed over sweeps 8..72 (one
+    recomputation inside)."""
+    t0 = time.perf_counter()
+    descs, _ = workloads.sk_gaussian_batch()
+    gen_s = time.perf_counter() - t0
+    ctx = sg.sg_create_sk(descs, t_max=workloads.SK_SWEEPS)
+    stream = torch.cuda.current_stream()
+    sg.sg_sweep(ctx, 8, stream)
+    torch.cuda.synchronize()
+    a0 = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)["accepted"].sum()
+    S = args.sk_gauss_sweeps
+    t0 = time.perf_counter()
+    sg.sg_sweep(ctx, S, stream)
+    res = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sg.sg_free(ctx)
+    n, reps = 4096, 2
+    upd = len(descs) * reps * n * S
+    acc = float(res["accepted"].sum() - a0) / upd
+    rate = upd / el
+    # bytes per attempted update: one float32 coupling row (4 N B) per
+    # accepted flip, the block's 64 x 64 tile (4 x 64 B per spin), and the
+    # direct recomputation (4 N^2 B per chain every 64 sweeps: 4 N / 64 B)
+    bpu = acc * 4 * n + 4 * 64 + 4 * n / 64
+    return dict(workload="SK Gaussian: 64 samples x 2 replicas, N=4096, J ~ N(0, 1/N) float32, fields in "
+                         "double, T=0.5, sweeps 8..%d" % (8 + S),
+                updates_per_ns=rate / 1e9, accepted_fraction=acc, generate_s=round(gen_s, 2),
+                roofline=dict(bound="hbm", bytes_per_update=round(bpu, 1),
+                              achieved=round(rate * bpu / 1e9, 1), unit="GB/s",
+                              frac=round(rate * bpu / HBM_PEAK_BPS, 4)))
+
+
 def run_uneven(args, torch, sg, workloads):
     """Uneven batch: 1024 VB instances, N log-uniform in [2^10, 2^20], 2 replicas,
     autotuned launch groups, graph-replayed sweep chunks; a steady window."""
@@ -249,15 +306,25 @@ def run_uneven(args, torch, sg, workloads):
     stream = torch.cuda.current_stream()
     sg.sg_sweep(ctx, 16, stream)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e0.record(stream)
     sg.sg_sweep(ctx, args.uneven_sweeps, stream)
+    e1.record(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     sg.sg_free(ctx)
     upd = sum(d.n for d in descs) * 2 * args.uneven_sweeps
+    # every instance has its own graph: 2 chains per unit (1 for the graphs
+    # whose two chains do not fit in one workgroup's LDS)
+    byts = sum(vb_bytes_per_sweep([d], 2, vb_chains_per_unit(d.n, 2)) for d in descs) * args.uneven_sweeps
+    dev_s = e0.elapsed_time(e1) * 1e-3
     return dict(workload="VB uneven: 1024 instances, N log-uniform in [2^10, 2^20], c=4, T in {0.6,0.8,1.0}, "
                          "2 replicas; sweeps 16..%d, autotuned, hipGraph" % (16 + args.uneven_sweeps),
-                updates_per_ns=upd / (el * 1e9), create_s=round(create_s, 2))
+                updates_per_ns=upd / (el * 1e9), create_s=round(create_s, 2),
+                roofline=dict(bound="hbm", achieved=round(byts / dev_s / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(byts / dev_s / HBM_PEAK_BPS, 4), bytes_per_update=round(byts / upd, 3),
+                              device_ms=round(dev_s * 1e3, 3)))
 
 
 def run_rrbg(args, torch, sg, workloads):
@@ -282,10 +349,53 @@ def run_rrbg(args, torch, sg, workloads):
     res = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
     sg.sg_free(ctx)
     upd = sum(d.n for d in descs) * 2 * S
+    byts = vb_bytes_per_sweep(descs, 2, 6) * S
     return dict(workload="VB RRBG: 256 random regular bipartite graphs (degree 4, N=65536, J=+-1) x "
                          "T{0.6,0.8,1.2} x 2 replicas; sweeps 64..%d" % (64 + S),
                 updates_per_ns=upd / (el * 1e9), generate_s=round(gen_s, 2), create_s=round(create_s, 2),
-                t_done=res["t_done"])
+                t_done=res["t_done"],
+                roofline=dict(bound="hbm", frac=round(byts / el / HBM_PEAK_BPS, 4), unit="GB/s",
+                              achieved=round(byts / el / 1e9, 1), bytes_per_update=round(byts / upd, 3)))
+
+
+def run_window(args, torch, sg, workloads):
+    """The batched configuration with the paper's windowed estimator of C
+    (SG_OPT_WINDOW, waiting times 0, 1, 2, 4, .., 2^12): after every sweep
+    each chain's overlap with each of the 14 stored waiting-time
+    configurations is added to its minor-third interval sum.  Timed past
+    t = 2^12, where every waiting time contributes."""
+    descs = workloads.vb_batched()
+    R, tw_max = 2, 4096
+    ctx = sg.sg_create_vb(descs, t_max=workloads.VB_BATCHED_SWEEPS, window_tw_max=tw_max)
+    stream = torch.cuda.current_stream()
+    sg.sg_sweep(ctx, tw_max + 1, stream)
+    torch.cuda.synchronize()
+    S = args.window_sweeps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sg.sg_sweep(ctx, S, stream)
+    e1.record(stream)
+    res = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sg.sg_free(ctx)
+    dev_s = e0.elapsed_time(e1) * 1e-3
+    n_total = sum(d.n for d in descs) * R
+    upd = n_total * S
+    kw = res["window"].shape[2]
+    # the sweep's own bytes plus the stored waiting-time words each unit reads
+    # per sweep: kw x (8 slots x N / 8) B per 6-chain unit
+    sweep_b = vb_bytes_per_sweep(descs, R, 6)
+    win_b = 256 * kw * 65536 * 8 / 8
+    byts = (sweep_b + win_b) * S
+    return dict(workload="VB batched with the windowed C estimator (%d waiting times <= 2^12, minor-third "
+                         "intervals of t_w + t): sweeps %d..%d" % (kw, tw_max + 1, tw_max + 1 + S),
+                updates_per_ns=upd / (el * 1e9), sweep_kernel_updates_per_ns=upd / (dev_s * 1e9),
+                roofline=dict(bound="hbm", achieved=round(byts / dev_s / 1e9, 1), peak=HBM_PEAK_GBS,
+                              unit="GB/s", frac=round(byts / dev_s / HBM_PEAK_BPS, 4),
+                              bytes_per_update=round(byts / upd, 3),
+                              window_bytes_per_update=round(win_b / n_total, 3)))
 
 
 def run_serving(args, torch, sg, workloads):
@@ -307,6 +417,64 @@ def run_serving(args, torch, sg, workloads):
     st.update(workload="serving: %d Poisson requests at 200/s, 70%% VB N in [2^12,2^20], 30%% SK N in "
                        "[512,8192], T~U[0.5,0.9], 256..1024 sweeps" % len(reqs),
               updates_per_ns=upd / (el * 1e9), wall_s=round(el, 2))
+    return st
+
+
+def served_bytes(results):
+    """Algorithmic bytes of the served runs: VB by the scope table's model
+    (one unit of the request's two chains streams its graph every sweep, two
+    units of one chain each when two chains do not fit in LDS, plus 1/4 B per
+    chain-update); SK by this library's model (one bit-packed coupling row of
+    N / 8 B per accepted flip, plus the int8 couplings the exact recompute
+    reads once per 64 sweeps for both chains)."""
+    total = 0.0
+    for r in results:
+        if r.kind == "vb":
+            units = 2 // vb_chains_per_unit(r.n, 2)
+            total += r.sweeps * (units * (4 * (r.n + 1) + 8 * math.floor(2.0 * r.n)) + 2 * r.n / 4.0)
+        else:
+            acc = float(r.obs["accepted"].sum())
+            total += acc * r.n / 8.0 + r.sweeps * r.n * r.n / 64.0
+    return total
+
+
+def run_serving_configured(args, torch, sg, workloads):
+    """Serving at the configured run lengths: 2^k sweeps, k uniform in
+    {12..16}, 70 % VB (N log-uniform in [2^12, 2^20]) and 30 % SK (N
+    log-uniform in [512, 8192]), T ~ U[0.5, 0.9], 2 replicas.  The capacity is
+    measured first, with every request arriving at once; the requests then
+    arrive as a Poisson process at 0.8 x that capacity (the same requests,
+    only the arrival times scaled)."""
+    import dataclasses
+    from paper_1906_11195_amd import serving
+    n_req = args.serve_full_requests
+    base = workloads.serving_requests(n_req, rate=1.0)
+
+    def serve(reqs, max_wall):
+        server = serving.AgingServer(hbm_budget=64 << 30, max_active=128, chunk_sweeps=4096, n_streams=8,
+                                     flags=sg.MEASURE_OBS)
+        t0 = time.perf_counter()
+        out = server.run(reqs, max_wall=max_wall)
+        return out, time.perf_counter() - t0
+
+    sat, w_sat = serve([dataclasses.replace(r, arrival=0.0) for r in base], args.serve_max_wall)
+    log("serving capacity: %d requests in %.1f s" % (len(sat), w_sat))
+    cap = len(sat) / w_sat
+    rate = 0.8 * cap
+    reqs = workloads.serving_requests(n_req, rate=rate)
+    res, wall = serve(reqs, args.serve_max_wall)
+    st = serving.latency_stats(res)
+    upd = sum(2 * r.n * r.sweeps for r in res)
+    byts = served_bytes(res)
+    st.update(workload="serving at configured lengths: %d Poisson requests at 0.8 x measured capacity "
+                       "(%.2f/s), 70%% VB N in [2^12,2^20], 30%% SK N in [512,8192], T~U[0.5,0.9], "
+                       "2^12..2^16 sweeps" % (len(reqs), rate),
+              capacity_per_s=round(cap, 3), capacity_wall_s=round(w_sat, 2), rate_per_s=round(rate, 3),
+              served=len(res), updates_per_ns=upd / (wall * 1e9), wall_s=round(wall, 2),
+              hbm=dict(achieved=round(byts / wall / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                       frac=round(byts / wall / HBM_PEAK_BPS, 4)),
+              p50_by_kind_ms={k: float(np.percentile([r.latency for r in res if r.kind == k], 50) * 1e3)
+                              for k in ("vb", "sk") if any(r.kind == k for r in res)})
     return st
 
 
@@ -379,11 +547,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-vb", action="store_true", help="the batched VB leg only (same as --legs vb)")
-    ap.add_argument("--legs", default="vb,plain,sk,uneven,rrbg,serving",
-                    help="comma-separated legs to run besides the headline: plain, sk, uneven, rrbg, serving")
+    ap.add_argument("--legs", default="vb,plain,sk,sk_gauss,uneven,rrbg,window,serving,serving_full",
+                    help="comma-separated legs to run besides the headline: plain, sk, sk_gauss, uneven, "
+                         "rrbg, window, serving, serving_full")
+    ap.add_argument("--sk-gauss-sweeps", type=int, default=64)
+    ap.add_argument("--skip-headline", action="store_true",
+                    help="run only the chosen legs (for profiling one leg; no headline value)")
     ap.add_argument("--uneven-sweeps", type=int, default=128)
     ap.add_argument("--rrbg-sweeps", type=int, default=512)
+    ap.add_argument("--window-sweeps", type=int, default=512)
     ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-full-requests", type=int, default=96)
+    ap.add_argument("--serve-max-wall", type=float, default=120.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -414,9 +589,11 @@ def main():
         print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
         return
     sg.library()
-    vb = run_vb_batched(args, torch, sg, workloads)
-    log("VB batched: %.1f updates/ns" % vb["value"])
-    plain = sk = uneven = rrbg = serve = None
+    vb = None
+    if not args.skip_headline:
+        vb = run_vb_batched(args, torch, sg, workloads)
+        log("VB batched: %.1f updates/ns" % vb["value"])
+    plain = sk = uneven = rrbg = serve = window = serve_full = sk_gauss = None
     legs = set() if args.only_vb else set(x.strip() for x in args.legs.split(","))
     if "plain" in legs:
         plain = run_vb_plain(args, torch, sg, workloads)
@@ -424,15 +601,29 @@ def main():
     if "sk" in legs:
         sk = run_sk(args, torch, sg, workloads)
         log("SK: %.2f updates/ns" % sk["updates_per_ns"])
+    if "sk_gauss" in legs:
+        sk_gauss = run_sk_gauss(args, torch, sg, workloads)
+        log("SK Gaussian: %.3f updates/ns" % sk_gauss["updates_per_ns"])
     if "uneven" in legs:
         uneven = run_uneven(args, torch, sg, workloads)
         log("VB uneven: %.1f updates/ns" % uneven["updates_per_ns"])
     if "rrbg" in legs:
         rrbg = run_rrbg(args, torch, sg, workloads)
         log("VB RRBG: %.1f updates/ns" % rrbg["updates_per_ns"])
+    if "window" in legs:
+        window = run_window(args, torch, sg, workloads)
+        log("VB windowed C: %.1f updates/ns" % window["updates_per_ns"])
     if "serving" in legs:
         serve = run_serving(args, torch, sg, workloads)
         log("serving: p50 %.1f ms, p99 %.1f ms" % (serve.get("p50_ms", 0), serve.get("p99_ms", 0)))
+    if "serving_full" in legs:
+        serve_full = run_serving_configured(args, torch, sg, workloads)
+        log("serving (configured lengths): p50 %.1f ms, p99 %.1f ms, %.1f updates/ns"
+            % (serve_full.get("p50_ms", 0), serve_full.get("p99_ms", 0), serve_full["updates_per_ns"]))
+    if vb is None:
+        print(json.dumps({"legs": dict(plain=plain, sk=sk, sk_gauss=sk_gauss, uneven=uneven, rrbg=rrbg, window=window,
+                                       serving=serve, serving_full=serve_full)}), flush=True)
+        return
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(args, workloads)
@@ -465,9 +656,12 @@ def main():
         "cpu_baseline": cpu,
         "plain": plain,
         "sk": sk,
+        "sk_gauss": sk_gauss,
         "uneven": uneven,
         "rrbg": rrbg,
+        "window": window,
         "serving": serve,
+        "serving_configured": serve_full,
     }
     print(json.dumps(out), flush=True)
 

@@ -125,12 +125,29 @@ typedef struct sg_vb_desc {
 } sg_vb_desc;
 
 /* One Sherrington-Kirkpatrick instance.
- *  n          number of spins, 2 <= n <= 32768 (the paper's largest SK size).
+ *  n          number of spins, 2 <= n <= 32768 (the paper's largest SK size;
+ *             n <= 16384 with real couplings).
  *  J          host int8[n][n] row-major, +-1, symmetric, zero diagonal; NULL
- *             to generate from (seed, graph_id).
+ *             to generate from (seed, graph_id).  Binary couplings +-1/sqrt(N)
+ *             (SI, SK section).
+ *  Jf         host float32[n][n] row-major, symmetric, zero diagonal, finite:
+ *             real couplings (Eq. 1 with Gaussian J_ij of variance 1/N, the
+ *             1/sqrt(N) included in the values); J must then be NULL.  The
+ *             energy is -sum_{i<j} Jf_ij s_i s_j; the local fields are kept in
+ *             IEEE double and a move with x = s_i h_i > 0 is accepted iff
+ *             r < floor(ldexp(exp(-beta (2 x)), 32)) (the binary rule with x
+ *             real).  A flip's change 2 s_i Jf_ij is added to every field in
+ *             flip order, as in the sequential sweep, so the fields are those
+ *             of the sequential definition until the first recomputation,
+ *             and equal to them within rounding (< 1e-12) after it.
+ *             Instances passing the same Jf pointer share one device copy.
+ *             All instances of a context have real couplings or none has.
  *  recompute_period  sweeps between exact recomputations of the local fields
- *             (0 selects 64); a mismatch with the incremental fields makes
- *             the next sg_measure return SG_EPARITY.
+ *             (0 selects 64); binary couplings: a mismatch with the
+ *             incremental fields makes the next sg_measure return
+ *             SG_EPARITY; real couplings: the recomputed fields replace the
+ *             incremental ones, and a difference above 1e-9 (1 + |h|)
+ *             returns SG_EPARITY.
  *  other fields as for sg_vb_desc. */
 typedef struct sg_sk_desc {
     int64_t n;
@@ -144,6 +161,7 @@ typedef struct sg_sk_desc {
     const int8_t* s0;
     int32_t recompute_period;
     int32_t reserved;
+    const float* Jf;
 } sg_sk_desc;
 
 /* Device memory callbacks (for instance a framework's caching allocator).
@@ -200,6 +218,15 @@ typedef struct sg_opts {
  * window / (window_count n) is C(tau, t_w) averaged over interval m.  Needs
  * t_max >= 1; VB contexts only (SG_ENOTSUP for SK). */
 #define SG_OPT_WINDOW 4u
+/* SG_OPT_MULTISPIN: the paper's multispin coding (Methods; SI bipartite-graph
+ * section): instances that share a graph -- generated from one (n, c, seed,
+ * graph_id), or passing one edges array with one seed, whatever J arrays they
+ * pass -- are packed 64 chains per work unit, one bit per chain in a 64-bit
+ * word per vertex, each chain with its own couplings, temperature and random
+ * streams, when they bring at least 16 chains and n <= 16384 (the words stay
+ * in LDS); other instances get the per-chain layout.  No effect on any
+ * result.  Not combined with SG_OPT_WINDOW (SG_ENOTSUP). */
+#define SG_OPT_MULTISPIN 8u
 
 #define SG_MEASURE_OBS 1u    /* times, bond, overlap, gram, accepted */
 #define SG_MEASURE_SPINS 2u  /* current spins, vertex order */
@@ -232,6 +259,8 @@ typedef struct sg_obs {
     int32_t n_bins;     /* its intervals */
     int64_t* window;    /* [count][n_replicas][kw][n_bins] overlap sums (SG_OPT_WINDOW) */
     int64_t* window_count;   /* [kw][n_bins] number of terms of each sum */
+    double* bond_real;  /* [count][n_replicas][k_cap] SK with real couplings: B = sum_{u<v}
+                           Jf_uv s_u s_v (energy -B; bond is then 0) */
 } sg_obs;
 
 /* Creates a context holding `count` VB instances on the current HIP device,

@@ -88,6 +88,9 @@ def _load():
         lib.orc_sk_run.argtypes = [i64, P, f64, u64, u32, i32, i32, P, i64, i64, i32,
                                    P, P, P, P, P, P, P]
         lib.orc_sk_run.restype = ctypes.c_int
+        lib.orc_skg_run.argtypes = [i64, P, f64, u64, u32, i32, i32, P, i64, i64, i32, i32,
+                                    P, P, P, P, P, P, P, P]
+        lib.orc_skg_run.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -262,6 +265,29 @@ def sk_run(n, J, T, seed, inst, n_rep, n_sweeps, t_max, start=START_RANDOM, s0=N
     if rc != 0:
         raise ValueError("orc_sk_run rejected its arguments")
     return _finish(o, n_rep)
+
+
+def skg_run(n, J, T, seed, inst, n_rep, n_sweeps, t_max, period=64, start=START_RANDOM, s0=None,
+            direct=False):
+    """One SK instance with real couplings (J float32 n x n), n_rep replicas
+    (see orc_skg_run): bond is the real sum B per replica and grid time,
+    `fields` the final local fields."""
+    J = np.ascontiguousarray(J, dtype=np.float32)
+    if s0 is not None:
+        s0 = np.ascontiguousarray(s0, dtype=np.int8).reshape(n_rep, n)
+    K = len(grid(t_max))
+    o = _outputs(n, n_rep, K)
+    o["bond"] = np.zeros((n_rep, K), np.float64)
+    h = np.zeros((n_rep, n), np.float64)
+    rc = _load().orc_skg_run(n, _ptr(J), float(T), seed, inst, n_rep, start, _ptr(s0), n_sweeps,
+                             t_max, int(period), 1 if direct else 0, _ptr(o["times"]), _ptr(o["bond"]),
+                             _ptr(o["overlap"]), _ptr(o["gram"]), _ptr(o["accepted"]),
+                             _ptr(o["spins"]), _ptr(h), ctypes.byref(o["k"]))
+    if rc != 0:
+        raise ValueError("orc_skg_run rejected its arguments")
+    out = _finish(o, n_rep)
+    out["fields"] = h
+    return out
 
 
 def vb_instance(n, c, seed, graph_id):

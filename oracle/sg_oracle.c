@@ -599,3 +599,132 @@ int orc_sk_run(int64_t n, const int8_t* J, double T, uint64_t seed, uint32_t ins
     free(snaps); free(s); free(H); free(thr);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sherrington-Kirkpatrick with real (Gaussian) couplings                    */
+/* ------------------------------------------------------------------------ */
+
+/* SK with real couplings J_ij (Eq. 1: Gaussian, variance 1/N; given here as
+ * float32, symmetric, zero diagonal, the 1/sqrt(N) already included), so the
+ * energy is H = -sum_{i<j} J_ij s_i s_j and flipping s_i changes it by
+ * dE = 2 x with x = s_i h_i, h_i = sum_j J_ij s_j.  Fields are kept in IEEE
+ * double: initially the direct sums (j ascending); after a flip of s_i,
+ * h_j += 2 s_i J_ij (new s_i) for every j, in flip order; every `period`
+ * sweeps (period > 0) they are recomputed directly (j ascending), as the
+ * paper's periodic recomputation of the fields prescribes for real
+ * couplings.  With direct != 0 every field is computed directly when it is
+ * used instead.  Acceptance as for the binary model with x real: flip if
+ * x <= 0, else iff r < floor(ldexp(exp(-(1/T) (2 x)), 32)) in double, r the
+ * same 32-bit uniform.  Outputs as orc_sk_run, except bond[n_rep][K] is the
+ * real B = sum_{i<j} J_ij s_i s_j (i ascending, then j), and h_out[n_rep][n]
+ * (may be NULL) receives the final fields.  Returns 0, or -1 on bad input. */
+int orc_skg_run(int64_t n, const float* J, double T, uint64_t seed, uint32_t inst,
+                int32_t n_rep, int32_t start, const int8_t* s0, int64_t n_sweeps,
+                int64_t t_max, int32_t period, int32_t direct, int64_t* times, double* bond,
+                int64_t* overlap, int64_t* gram, int64_t* accepted, int8_t* spins,
+                double* h_out, int32_t* k_done)
+{
+    if (n < 1 || n_rep < 1 || n_sweeps < 0 || t_max < 0 || period < 0) return -1;
+    const double beta = 1.0 / T;
+    int64_t grid[70];
+    int32_t K = orc_grid(t_max, grid);
+    for (int32_t k = 0; k < K; ++k) times[k] = grid[k];
+    int8_t* snaps = (int8_t*)malloc((size_t)n_rep * (size_t)K * (size_t)n);
+    int8_t* s = (int8_t*)malloc((size_t)n);
+    double* H = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t kd = 0;
+
+    for (int32_t r = 0; r < n_rep; ++r) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (start == 0) s[i] = (int8_t)orc_init_spin(seed, inst, (uint32_t)r, (uint64_t)i);
+            else if (start == 1) s[i] = 1;
+            else s[i] = s0[(int64_t)r * n + i];
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            double h = 0.0;
+            for (int64_t j = 0; j < n; ++j) h += (double)J[i * n + j] * (double)s[j];
+            H[i] = h;
+        }
+        accepted[r] = 0;
+        int32_t k = 0;
+        for (int64_t t = 0;; ++t) {
+            if (t <= t_max && is_grid_time(t)) {
+                memcpy(snaps + ((int64_t)r * K + k) * n, s, (size_t)n);
+                double B = 0.0;
+                for (int64_t i = 0; i < n; ++i)
+                    for (int64_t j = i + 1; j < n; ++j) B += (double)J[i * n + j] * (double)(s[i] * s[j]);
+                bond[(int64_t)r * K + k] = B;
+                ++k;
+            }
+            if (t == n_sweeps) break;
+            for (int64_t i = 0; i < n; ++i) {
+                double h;
+                if (direct) {
+                    h = 0.0;
+                    for (int64_t j = 0; j < n; ++j) h += (double)J[i * n + j] * (double)s[j];
+                } else {
+                    h = H[i];
+                }
+                const double x = (double)s[i] * h;
+                int flip;
+                if (x <= 0.0) {
+                    flip = 1;
+                } else {
+                    const double p = exp(-beta * (2.0 * x));
+                    const uint64_t thr = (uint64_t)floor(ldexp(p, 32));
+                    flip = (uint64_t)orc_accept_uniform(seed, inst, (uint32_t)r, (uint32_t)t, (uint64_t)i) < thr;
+                }
+                if (flip) {
+                    s[i] = (int8_t)-s[i];
+                    accepted[r]++;
+                    if (!direct) {
+                        const double a = 2.0 * (double)s[i];
+                        for (int64_t j = 0; j < n; ++j) H[j] += a * (double)J[i * n + j];
+                    }
+                }
+            }
+            if (period > 0 && (t + 1) % period == 0 && !direct)
+                for (int64_t i = 0; i < n; ++i) {
+                    double h = 0.0;
+                    for (int64_t j = 0; j < n; ++j) h += (double)J[i * n + j] * (double)s[j];
+                    H[i] = h;
+                }
+        }
+        kd = k;
+        memcpy(spins + (int64_t)r * n, s, (size_t)n);
+        if (h_out)
+            for (int64_t i = 0; i < n; ++i) {
+                double h = H[i];
+                if (direct) {
+                    h = 0.0;
+                    for (int64_t j = 0; j < n; ++j) h += (double)J[i * n + j] * (double)s[j];
+                }
+                h_out[(int64_t)r * n + i] = h;
+            }
+    }
+
+    int64_t pair = 0;
+    for (int32_t a = 0; a < n_rep; ++a)
+        for (int32_t b = a + 1; b < n_rep; ++b, ++pair)
+            for (int32_t k = 0; k < kd; ++k) {
+                const int8_t* sa = snaps + ((int64_t)a * K + k) * n;
+                const int8_t* sb = snaps + ((int64_t)b * K + k) * n;
+                int64_t Q = 0;
+                for (int64_t i = 0; i < n; ++i) Q += sa[i] * sb[i];
+                overlap[pair * K + k] = Q;
+            }
+    for (int32_t r = 0; r < n_rep; ++r)
+        for (int32_t k = 0; k < K; ++k)
+            for (int32_t l = 0; l < K; ++l) {
+                int64_t G = 0;
+                if (k < kd && l < kd) {
+                    const int8_t* sk = snaps + ((int64_t)r * K + k) * n;
+                    const int8_t* sl = snaps + ((int64_t)r * K + l) * n;
+                    for (int64_t i = 0; i < n; ++i) G += sk[i] * sl[i];
+                }
+                gram[((int64_t)r * K + k) * K + l] = G;
+            }
+    *k_done = kd;
+    free(snaps); free(s); free(H);
+    return 0;
+}

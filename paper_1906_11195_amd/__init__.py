@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libsgmi.so")
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE, SG_ESTATE, SG_EPARITY, SG_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 START_RANDOM, START_ALIGNED, START_GIVEN = 0, 1, 2
 MEASURE_OBS, MEASURE_SPINS = 1, 2
-OPT_AUTOTUNE, OPT_GRAPH, OPT_WINDOW = 1, 2, 4
+OPT_AUTOTUNE, OPT_GRAPH, OPT_WINDOW, OPT_MULTISPIN = 1, 2, 4, 8
 
 EXPORTS = ("sg_create_vb", "sg_create_sk", "sg_sweep", "sg_measure", "sg_measure_noalloc", "sg_free",
            "sg_strerror", "sg_vb_inspect", "sg_sk_inspect", "sg_sk_corrupt_field")
@@ -47,7 +47,8 @@ class _SkDesc(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("instance_id", ctypes.c_uint32),
                 ("graph_id", ctypes.c_uint32), ("n_replicas", ctypes.c_int32),
                 ("start", ctypes.c_int32), ("s0", ctypes.c_void_p),
-                ("recompute_period", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("recompute_period", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("Jf", ctypes.c_void_p)]
 
 
 class _Opts(ctypes.Structure):
@@ -63,7 +64,7 @@ class _Obs(ctypes.Structure):
                 ("times", ctypes.c_void_p), ("bond", ctypes.c_void_p), ("overlap", ctypes.c_void_p),
                 ("gram", ctypes.c_void_p), ("accepted", ctypes.c_void_p), ("spins", ctypes.c_void_p),
                 ("kw", ctypes.c_int32), ("n_bins", ctypes.c_int32), ("window", ctypes.c_void_p),
-                ("window_count", ctypes.c_void_p)]
+                ("window_count", ctypes.c_void_p), ("bond_real", ctypes.c_void_p)]
 
 
 class _VbTables(ctypes.Structure):
@@ -162,9 +163,10 @@ class SkDesc:
     graph_id: int = 0
     n_replicas: int = 2
     start: int = START_RANDOM
-    J: Optional[np.ndarray] = None         # [n, n] int8
+    J: Optional[np.ndarray] = None         # [n, n] int8 (binary couplings)
     s0: Optional[np.ndarray] = None
     recompute_period: int = 64
+    Jf: Optional[np.ndarray] = None        # [n, n] float32 (real couplings)
 
 
 def _vb_struct(d: VbDesc, keep: list) -> _VbDesc:
@@ -193,6 +195,10 @@ def _sk_struct(d: SkDesc, keep: list) -> _SkDesc:
         J = np.ascontiguousarray(d.J, dtype=np.int8).reshape(-1)
         keep.append(J)
         s.J = J.ctypes.data
+    if d.Jf is not None:
+        Jf = np.ascontiguousarray(d.Jf, dtype=np.float32).reshape(-1)
+        keep.append(Jf)
+        s.Jf = Jf.ctypes.data
     if d.s0 is not None:
         s0 = np.ascontiguousarray(d.s0, dtype=np.int8).reshape(-1)
         keep.append(s0)
@@ -249,9 +255,10 @@ def _stream_handle(stream):
 class Context:
     """Owning handle of an sg_ctx."""
 
-    def __init__(self, ptr, kind, ns, R, K, kw=0, n_bins=0):
+    def __init__(self, ptr, kind, ns, R, K, kw=0, n_bins=0, real=False):
         self.ptr = ptr
         self.kind = kind
+        self.real = real        # SK with real couplings: bond_real instead of bond
         self.ns = list(ns)
         self.R = R
         self.K = K
@@ -278,12 +285,14 @@ def _grid_len(t_max):
 def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
                  threads_per_unit: int = 0, torch_alloc: bool = True, autotune: bool = False,
                  graph: bool = False, split_members: int = 0,
-                 window_tw_max: Optional[int] = None) -> Context:
+                 window_tw_max: Optional[int] = None, multispin: bool = False) -> Context:
     """window_tw_max: measure the windowed correlation with the grid times
-    <= window_tw_max as waiting times (SG_OPT_WINDOW)."""
+    <= window_tw_max as waiting times (SG_OPT_WINDOW); multispin: pack the
+    chains of a shared graph 64 per word (SG_OPT_MULTISPIN)."""
     keep = []
     arr = (_VbDesc * len(descs))(*[_vb_struct(d, keep) for d in descs])
     flags = (OPT_AUTOTUNE if autotune else 0) | (OPT_GRAPH if graph else 0)
+    flags |= OPT_MULTISPIN if multispin else 0
     kw = n_bins = 0
     if window_tw_max is not None:
         flags |= OPT_WINDOW
@@ -305,7 +314,8 @@ def sg_create_sk(descs: Sequence[SkDesc], t_max: int, threads_per_unit: int = 0,
     out = ctypes.c_void_p()
     _check(library().sg_create_sk(ctypes.byref(arr), len(descs), ctypes.byref(o), ctypes.byref(out)),
            "sg_create_sk")
-    return Context(out, "sk", [d.n for d in descs], descs[0].n_replicas, _grid_len(t_max))
+    return Context(out, "sk", [d.n for d in descs], descs[0].n_replicas, _grid_len(t_max),
+                   real=descs[0].Jf is not None)
 
 
 def sg_sweep(ctx: Context, n_sweeps: int, stream=None) -> None:
@@ -324,6 +334,9 @@ def sg_measure(ctx: Context, flags: int = MEASURE_OBS, stream=None, check: bool 
         o.times, o.bond, o.gram = _p(res["times"]), _p(res["bond"]), _p(res["gram"])
         o.accepted = _p(res["accepted"])
         o.overlap = _p(res["overlap"]) if npair else None
+    if ctx.real and flags & MEASURE_OBS:
+        res["bond_real"] = np.zeros((count, R, K), np.float64)
+        o.bond_real = _p(res["bond_real"])
     if ctx.kw and flags & MEASURE_OBS:
         res["window"] = np.zeros((count, R, ctx.kw, ctx.n_bins), np.int64)
         res["window_count"] = np.zeros((ctx.kw, ctx.n_bins), np.int64)
@@ -363,6 +376,9 @@ def sg_measure_noalloc(ctx: Context, stream=None, check: bool = True) -> dict:
         res["window"] = np.zeros((count, R, ctx.kw, ctx.n_bins), np.int64)
         res["window_count"] = np.zeros((ctx.kw, ctx.n_bins), np.int64)
         o.window, o.window_count = _p(res["window"]), _p(res["window_count"])
+    if ctx.real:
+        res["bond_real"] = np.zeros((count, R, K), np.float64)
+        o.bond_real = _p(res["bond_real"])
     code = library().sg_measure_noalloc(ctx.ptr, ctypes.byref(o), _stream_handle(stream))
     res["status"] = code
     if check:

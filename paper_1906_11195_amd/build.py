@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsgmi.so")
-SOURCES = ["sg_host.cpp", "sg_vb.hip", "sg_sk.hip", "sg_measure.hip"]
+SOURCES = ["sg_host.cpp", "sg_vb.hip", "sg_vbm.hip", "sg_sk.hip", "sg_skg.hip", "sg_measure.hip"]
 ARCH = "gfx950"
 
 

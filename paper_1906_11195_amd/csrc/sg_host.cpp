@@ -63,6 +63,7 @@ struct VbGraph {
     std::vector<int32_t> order;      // vertex at each position
     std::vector<int32_t> row;        // [n+1], sweep order
     std::vector<uint32_t> ent;       // [2m]
+    std::vector<int32_t> eix;        // [2m] edge index of each adjacency entry
     std::vector<int32_t> cls;        // [ncls+1]
     int32_t ncls = 0;
     int32_t max_degree = 0;
@@ -119,13 +120,15 @@ void vb_tables(VbGraph& g)
     }
     std::vector<int64_t> vstart((size_t)n + 1, 0);
     for (int64_t v = 0; v < n; ++v) vstart[(size_t)v + 1] = vstart[(size_t)v] + deg[(size_t)v];
-    std::vector<int32_t> vn(2 * m);
+    std::vector<int32_t> vn(2 * m), ve(2 * m);
     std::vector<int8_t> vj(2 * m);
     std::vector<int64_t> fill(vstart.begin(), vstart.end() - 1);
     for (size_t e = 0; e < m; ++e) {
         const int32_t u = g.eu[e], v = g.ev[e];
+        ve[(size_t)fill[(size_t)u]] = (int32_t)e;
         vn[(size_t)fill[(size_t)u]] = v;
         vj[(size_t)fill[(size_t)u]++] = g.J[e];
+        ve[(size_t)fill[(size_t)v]] = (int32_t)e;
         vn[(size_t)fill[(size_t)v]] = u;
         vj[(size_t)fill[(size_t)v]++] = g.J[e];
     }
@@ -169,13 +172,16 @@ void vb_tables(VbGraph& g)
     }
     g.row.assign((size_t)n + 1, 0);
     g.ent.resize(2 * m);
+    g.eix.resize(2 * m);
     int64_t e = 0;
     for (int64_t p = 0; p < n; ++p) {
         const int32_t v = g.order[(size_t)p];
         g.row[(size_t)p] = (int32_t)e;
-        for (int64_t a = vstart[(size_t)v]; a < vstart[(size_t)v + 1]; ++a)
+        for (int64_t a = vstart[(size_t)v]; a < vstart[(size_t)v + 1]; ++a) {
+            g.eix[(size_t)e] = ve[(size_t)a];
             g.ent[(size_t)e++] = (uint32_t)pos[(size_t)vn[(size_t)a]] |
                                  (vj[(size_t)a] < 0 ? 0x80000000u : 0u);
+        }
     }
     g.row[(size_t)n] = (int32_t)e;
 }
@@ -234,6 +240,18 @@ void build_vb_graph(const sg_vb_desc& d, VbGraph& g)
 void check_sk_desc(const sg_sk_desc& d)
 {
     if (d.n < 2 || d.n > 32768) fail(d.n > 32768 ? SG_ENOTSUP : SG_EINVAL);
+    if (d.Jf) {
+        if (d.J) fail(SG_EINVAL);
+        if (d.n > 16384) fail(SG_ENOTSUP);   // fields in double stay in one workgroup's LDS
+        const int64_t n = d.n;
+        for (int64_t i = 0; i < n; ++i) {
+            if (d.Jf[i * n + i] != 0.0f) fail(SG_EINVAL);
+            for (int64_t j = i + 1; j < n; ++j) {
+                const float a = d.Jf[i * n + j];
+                if (!std::isfinite(a) || d.Jf[j * n + i] != a) fail(SG_EINVAL);
+            }
+        }
+    }
     if (!finite_nonneg_T(d.T)) fail(SG_EINVAL);
     if (d.n_replicas < 1 || d.n_replicas > kVbMaxChains) fail(SG_EINVAL);
     if (d.start < SG_START_RANDOM || d.start > SG_START_GIVEN) fail(SG_EINVAL);
@@ -398,6 +416,7 @@ struct sg_ctx {
         size_t lds = 0;
         int32_t first = 0, count = 0;     // range in units_d
         bool split = false;               // members of split units (not autotuned)
+        bool multispin = false;           // multispin units: range in vbm_d
         int64_t updates = 0;              // chain-updates per sweep
         hipStream_t stream = nullptr;     // own stream for groups after the first
         hipEvent_t done = nullptr;
@@ -408,6 +427,11 @@ struct sg_ctx {
     uint32_t* bars_d = nullptr;           // split units' barrier words, 2 per unit
     int n_bar = 0;
     int split_held = 0;                   // members reserved in the process-wide ledger
+    // multispin units (SG_OPT_MULTISPIN): up to 64 chains of one graph per word
+    std::vector<VbmUnit> vbm;
+    VbmUnit* vbm_d = nullptr;
+    int32_t* vbm_ids_d = nullptr;         // [units][64] chain ids
+    std::vector<char> chain_ms;           // chain lives in a multispin unit (chain_loc indexes vbm)
     bool use_graph = false;
     hipStream_t capture_stream = nullptr; // for capturing when the caller uses the null stream
     std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;   // chunk length -> executable
@@ -421,6 +445,9 @@ struct sg_ctx {
     int period = 64;
     int* err_d = nullptr;
     int sk_threads = 256;
+    bool sk_real = false;                 // SK with real couplings (sg_skg.hip)
+    double* bondr_d = nullptr;            // [n_chains][K] real bond sums
+    double* bpart_d = nullptr;            // their partial sums
     // measurement
     MeasureChain* mc_d = nullptr;
     int32_t* pairs_d = nullptr;
@@ -528,8 +555,12 @@ void vb_launch_chunk(sg_ctx* c, int32_t nsw, hipStream_t s, const int64_t* t0p, 
     }
     for (size_t gi = 0; gi < ng; ++gi) {
         const sg_ctx::Group& G = c->groups[gi];
-        hip_check(vb_sweep(c->units_d + G.first, G.count, G.threads, G.lds, t0p, nsw, c->t_max,
-                           gi == 0 ? s : G.stream));
+        if (G.multispin)
+            hip_check(vbm_sweep(c->vbm_d + G.first, G.count, G.threads, G.lds, t0p, nsw, c->t_max,
+                                gi == 0 ? s : G.stream));
+        else
+            hip_check(vb_sweep(c->units_d + G.first, G.count, G.threads, G.lds, t0p, nsw, c->t_max,
+                               gi == 0 ? s : G.stream));
     }
     for (size_t gi = 1; gi < ng; ++gi) {
         hip_check(hipEventRecord(c->groups[gi].done, c->groups[gi].stream));
@@ -608,7 +639,7 @@ void vb_autotune(sg_ctx* c)
     hip_check(hipEventCreate(&e0));
     hip_check(hipEventCreate(&e1));
     for (auto& G : c->groups) {
-        if (G.split) continue;   // members must meet at their barriers: keep the planned size
+        if (G.split || G.multispin) continue;   // split members meet at barriers; multispin: planned size
         int32_t nmax = 0;
         for (int32_t u = G.first; u < G.first + G.count; ++u) nmax = std::max(nmax, c->units[(size_t)u].n);
         const VbUnit& U0 = c->units[(size_t)G.first];
@@ -712,9 +743,32 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     std::map<std::tuple<int64_t, int64_t, const int32_t*, const int8_t*, uint64_t>, int32_t> explicit_of;
     std::vector<int32_t> first_inst;   // representative desc per group
     c->group_of_inst.resize((size_t)count);
+    // Multispin (SG_OPT_MULTISPIN): instances that share a graph -- generated
+    // from one key, or passing one edge array with one seed -- whatever their
+    // couplings, when they bring at least kVbmMinChains chains and the graph
+    // fits (n <= kVbmMaxN), form multispin groups; the others are grouped as
+    // usual.
+    const bool ms_opt = o && (o->flags & SG_OPT_MULTISPIN);
+    if (ms_opt && c->kw > 0) fail(SG_ENOTSUP);
+    constexpr int32_t kVbmMinChains = 16;
+    std::vector<char> in_ms((size_t)count, 0);
+    if (ms_opt) {
+        std::map<std::tuple<int64_t, int64_t, const int32_t*, uint64_t, uint64_t, uint32_t>, int32_t> cnt;
+        auto mk = [&](int32_t i) {
+            uint64_t cb;
+            std::memcpy(&cb, &d[i].c, 8);
+            return d[i].edges ? std::make_tuple((int64_t)d[i].n, d[i].n_edges, d[i].edges, d[i].seed, (uint64_t)0, 0u)
+                              : std::make_tuple((int64_t)d[i].n, (int64_t)-1, (const int32_t*)nullptr, d[i].seed, cb,
+                                                d[i].graph_id);
+        };
+        for (int32_t i = 0; i < count; ++i) cnt[mk(i)] += c->R;
+        for (int32_t i = 0; i < count; ++i)
+            in_ms[(size_t)i] = cnt[mk(i)] >= kVbmMinChains && d[i].n <= kVbmMaxN;
+    }
     for (int32_t i = 0; i < count; ++i) {
         if (d[i].edges) {
-            const auto ek = std::make_tuple((int64_t)d[i].n, d[i].n_edges, d[i].edges, d[i].J, d[i].seed);
+            const int8_t* jkey = in_ms[(size_t)i] ? nullptr : d[i].J;   // multispin: couplings per chain
+            const auto ek = std::make_tuple((int64_t)d[i].n, d[i].n_edges, d[i].edges, jkey, d[i].seed);
             auto it = explicit_of.find(ek);
             if (it == explicit_of.end()) {
                 it = explicit_of.emplace(ek, (int32_t)first_inst.size()).first;
@@ -762,9 +816,12 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     // wavefronts busy; packing them at the cost of wavefronts leaves one
     // latency-bound unit that finishes long after the rest.)
     auto rpad_of = [](int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : 8; };
+    std::vector<char> group_ms(n_groups, 0);
+    for (size_t gi = 0; gi < n_groups; ++gi) group_ms[gi] = in_ms[(size_t)first_inst[gi]];
     std::vector<int> graph_threads(n_groups, 64);
     std::vector<UnitPlan> plan;
     for (size_t gi = 0; gi < n_groups; ++gi) {
+        if (group_ms[gi]) continue;   // multispin units are planned below
         const VbGraph& g = graphs[gi];
         const int64_t n = g.n;
         int th = 64;
@@ -914,7 +971,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     if (c->kw > 0)
         for (size_t u = 0; u < plan.size(); ++u) {
             const int64_t n = graphs[(size_t)plan[u].group].n;
-            off_wsnap[u] = A.take((size_t)VbLayout(plan[u].rpad).words(n) * 4 * (size_t)c->kw);
+            off_wsnap[u] = A.take((size_t)((VbLayout(plan[u].rpad).words(n) + 3) & ~3) * 4 * (size_t)c->kw);
         }
     const size_t win_per_chain = (size_t)c->kw * (size_t)c->n_bins;
     const size_t off_win = A.take(std::max<size_t>(1, (size_t)c->n_chains * win_per_chain) * 8);
@@ -930,6 +987,32 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     const size_t off_gram = A.take((size_t)c->n_chains * c->K * c->K * 8);
     const size_t off_acc = A.take((size_t)c->n_chains * 8);
     const size_t off_t = A.take(16);
+
+    // multispin units: the chains of each multispin group, 64 per unit
+    struct MsPlan {
+        int32_t group;
+        std::vector<int32_t> chains;
+    };
+    std::vector<MsPlan> ms_plan;
+    for (size_t gi = 0; gi < n_groups; ++gi) {
+        if (!group_ms[gi]) continue;
+        const auto& ch = chains_of[gi];
+        for (size_t a = 0; a < ch.size(); a += (size_t)kVbmChains) {
+            MsPlan mp;
+            mp.group = (int32_t)gi;
+            mp.chains.assign(ch.begin() + (long)a, ch.begin() + (long)std::min(ch.size(), a + (size_t)kVbmChains));
+            ms_plan.push_back(std::move(mp));
+        }
+    }
+    std::vector<size_t> off_mjw(ms_plan.size()), off_mst(ms_plan.size()), off_mthr(ms_plan.size());
+    for (size_t u = 0; u < ms_plan.size(); ++u) {
+        const VbGraph& g = graphs[(size_t)ms_plan[u].group];
+        off_mjw[u] = A.take((g.ent.size() + kVbEntPad) * 8);
+        off_mst[u] = A.take((size_t)g.n * 8);
+        off_mthr[u] = A.take((size_t)2 * kVbmChains * kVbXMax * 4);
+    }
+    const size_t off_vbm = A.take(std::max<size_t>(1, ms_plan.size()) * sizeof(VbmUnit));
+    const size_t off_vbm_ids = A.take(std::max<size_t>(1, ms_plan.size()) * kVbmChains * 4);
 
     c->arena_bytes = A.size;
     c->arena = c->dev_alloc(A.size);
@@ -1031,6 +1114,99 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         c->bond_lds = std::max(c->bond_lds, (size_t)(((U.nch * U.words_n + 1) & ~1) * 4 + kVbMaxChains * 8));
         c->updates_per_sweep += g.n * U.nch;
     }
+    // multispin units: descriptors, coupling words (bit k of entry e: the
+    // coupling of slot k's chain on that entry is -1) and threshold tables
+    c->chain_ms.assign((size_t)c->n_chains, 0);
+    std::vector<int32_t> ms_ids(std::max<size_t>(1, ms_plan.size()) * kVbmChains, 0);
+    c->vbm.resize(ms_plan.size());
+    int ms_threads = 128;
+    int64_t ms_updates = 0;
+    parallel_for(ms_plan.size(), [&](size_t u) {
+        hip_check(hipSetDevice(c->device));   // a worker thread: the context's device
+        const MsPlan& mp = ms_plan[u];
+        const VbGraph& g = graphs[(size_t)mp.group];
+        VbmUnit U;
+        std::memset(&U, 0, sizeof(U));
+        U.row = c->at<int32_t>(off_row[(size_t)mp.group]);
+        U.ent = c->at<uint32_t>(off_ent[(size_t)mp.group]);
+        U.cls = c->at<int32_t>(off_cls[(size_t)mp.group]);
+        U.jw = c->at<uint64_t>(off_mjw[u]);
+        U.state = c->at<uint64_t>(off_mst[u]);
+        U.thr = c->at<uint32_t>(off_mthr[u]);
+        U.n = (int32_t)g.n;
+        U.ncls = g.ncls;
+        U.nch = (int32_t)mp.chains.size();
+        U.words_n = (int32_t)((g.n + 31) / 32);
+        U.key = U.seed = d[mp.chains[0] / c->R].seed;
+        if (g.ncls > 64) fail(SG_ENOTSUP);
+        std::vector<uint32_t> thr((size_t)2 * kVbmChains * kVbXMax, 0u);   // high halves, then low halves
+        std::vector<uint64_t> jw(g.ent.size() + kVbEntPad, 0ull);
+        for (int32_t k = 0; k < U.nch; ++k) {
+            const int32_t ch = mp.chains[(size_t)k];
+            const int32_t i = ch / c->R, r = ch % c->R;
+            if (d[i].seed != U.key) fail(SG_EINVAL);
+            U.snap[k] = c->at<uint32_t>(off_snap[(size_t)ch]);
+            U.accepted[k] = c->at<unsigned long long>(off_acc) + ch;
+            U.inst[k] = d[i].instance_id;
+            U.rep[k] = (uint32_t)r;
+            U.init_mode[k] = d[i].start;
+            U.given[k] = d[i].start == SG_START_GIVEN ? c->at<uint32_t>(off_given[(size_t)ch]) : nullptr;
+            ms_ids[u * kVbmChains + (size_t)k] = ch;
+            for (int32_t x = 1; x < kVbXMax; ++x) {
+                const uint64_t th = threshold(d[i].T, 1.0, x);   // up to 2^32 (T = inf)
+                thr[(size_t)k * kVbXMax + (size_t)x] = (uint32_t)(th >> 16);
+                thr[(size_t)(kVbmChains + k) * kVbXMax + (size_t)x] = (uint32_t)(th & 0xffffu);
+            }
+            const int8_t* Ji = d[i].edges ? d[i].J : nullptr;
+            const uint64_t bit = 1ull << k;
+            for (size_t e = 0; e < g.ent.size(); ++e) {
+                const bool neg = Ji ? Ji[(size_t)g.eix[e]] < 0 : (g.ent[e] >> 31) != 0u;
+                if (neg) jw[e] |= bit;
+            }
+        }
+        hip_check(hipMemcpy(c->at<void>(off_mthr[u]), thr.data(), thr.size() * 4, hipMemcpyHostToDevice));
+        hip_check(hipMemcpy(c->at<void>(off_mjw[u]), jw.data(), jw.size() * 8, hipMemcpyHostToDevice));
+        c->vbm[u] = U;
+    });
+    for (size_t u = 0; u < ms_plan.size(); ++u) {
+        const MsPlan& mp = ms_plan[u];
+        const VbGraph& g = graphs[(size_t)mp.group];
+        for (size_t k = 0; k < mp.chains.size(); ++k) {
+            c->chain_loc[(size_t)mp.chains[k]] = {(int32_t)u, (int32_t)k};
+            c->chain_ms[(size_t)mp.chains[k]] = 1;
+        }
+        ms_updates += g.n * (int64_t)mp.chains.size();
+        // wavefronts: about three 64-position chunks each in the largest
+        // colour class (2 to 16), within LDS
+        int32_t maxcls = 0;
+        for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
+        const int32_t chunks = (maxcls + 63) / 64;
+        int waves = 2;
+        while (waves < 16 && waves * 3 < chunks) waves *= 2;
+        ms_threads = std::max(ms_threads, 64 * waves);
+    }
+    if (!ms_plan.empty()) {
+        const size_t lds_cap = 160 * 1024 - 1024;
+        int32_t nmax = 0;
+        for (const auto& U : c->vbm) nmax = std::max(nmax, U.n);
+        while (ms_threads > 128 && vbm_lds_bytes(nmax, ms_threads) > lds_cap) ms_threads /= 2;
+        if (vbm_lds_bytes(nmax, ms_threads) > lds_cap) fail(SG_ENOTSUP);
+        sg_ctx::Group G;
+        G.threads = ms_threads;
+        G.lds = vbm_lds_bytes(nmax, ms_threads);
+        G.first = 0;
+        G.count = (int32_t)ms_plan.size();
+        G.multispin = true;
+        G.updates = ms_updates;
+        c->groups.push_back(G);
+        c->updates_per_sweep += ms_updates;
+    }
+    c->vbm_d = c->at<VbmUnit>(off_vbm);
+    c->vbm_ids_d = c->at<int32_t>(off_vbm_ids);
+    if (!ms_plan.empty()) {
+        hip_check(hipMemcpy(c->vbm_d, c->vbm.data(), c->vbm.size() * sizeof(VbmUnit), hipMemcpyHostToDevice));
+        hip_check(hipMemcpy(c->vbm_ids_d, ms_ids.data(), ms_ids.size() * 4, hipMemcpyHostToDevice));
+    }
     c->order_of_group.resize(n_groups);
     for (size_t gi = 0; gi < n_groups; ++gi) c->order_of_group[gi] = std::move(graphs[gi].order);
 
@@ -1061,7 +1237,15 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         hip_check(hipMemcpy(c->pairs_d, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
     c->t_dev = c->at<int64_t>(off_t);
     c->win_d = c->at<long long>(off_win);
-    if (c->kw > 0) hip_check(zero_i64(c->win_d, (size_t)c->n_chains * win_per_chain, nullptr));
+    if (c->kw > 0) {
+        hip_check(zero_i64(c->win_d, (size_t)c->n_chains * win_per_chain, nullptr));
+        // waiting-time words: rows padded to 16 bytes with zeros
+        for (size_t u = 0; u < plan.size(); ++u) {
+            const int64_t n = graphs[(size_t)plan[u].group].n;
+            const size_t row = (size_t)((VbLayout(plan[u].rpad).words(n) + 3) & ~3);
+            hip_check(zero_i64(c->at<long long>(off_wsnap[u]), row * (size_t)c->kw / 2, nullptr));
+        }
+    }
     hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
     hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
     hip_check(zero_i64((long long*)c->t_dev, 2, nullptr));
@@ -1069,6 +1253,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     hip_check(zero_i64((long long*)c->err_d, 1, nullptr));
     hip_check(vb_init(c->units_d, (int)c->units.size(), 256, 0, nullptr));
     hip_check(vb_prepare());
+    hip_check(vbm_init(c->vbm_d, (int)c->vbm.size(), nullptr));
+    hip_check(vbm_prepare());
     // every launch group after the first runs on a stream of its own, forked
     // from and joined back into the caller's stream
     for (size_t gi = 1; gi < c->groups.size(); ++gi) {
@@ -1082,13 +1268,156 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     if (o && (o->flags & SG_OPT_AUTOTUNE) && !o->threads_per_unit) vb_autotune(c);
 }
 
+// SK with real couplings: float32 J per distinct array, fields in double.
+void create_skg(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
+{
+    c->kind = 1;
+    c->sk_real = true;
+    c->count = count;
+    c->R = d[0].n_replicas;
+    c->period = d[0].recompute_period ? d[0].recompute_period : 64;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!d[i].Jf) fail(SG_EINVAL);   // a context is all real or all binary
+        check_sk_desc(d[i]);
+        if (d[i].n_replicas != c->R) fail(SG_EINVAL);
+        if ((d[i].recompute_period ? d[i].recompute_period : 64) != c->period) fail(SG_EINVAL);
+    }
+    setup_common(c, o);
+    if (c->kw > 0) fail(SG_ENOTSUP);   // the windowed correlation is measured for VB only
+    c->n_chains = count * c->R;
+    c->n_of.resize((size_t)count);
+    // instances passing the same array share its device copy
+    std::map<std::pair<const float*, int64_t>, int32_t> share;
+    std::vector<int32_t> jslot((size_t)count);
+    std::vector<int32_t> jrep;
+    for (int32_t i = 0; i < count; ++i) {
+        c->n_of[(size_t)i] = d[i].n;
+        const auto key = std::make_pair(d[i].Jf, d[i].n);
+        auto it = share.find(key);
+        if (it == share.end()) {
+            it = share.emplace(key, (int32_t)jrep.size()).first;
+            jrep.push_back(i);
+        }
+        jslot[(size_t)i] = it->second;
+    }
+    Arena A;
+    std::vector<size_t> off_J(jrep.size());
+    for (size_t j = 0; j < jrep.size(); ++j) off_J[j] = A.take((size_t)(d[jrep[j]].n * d[jrep[j]].n) * 4);
+    std::vector<size_t> off_state((size_t)c->n_chains), off_H((size_t)c->n_chains), off_snap((size_t)c->n_chains),
+        off_given((size_t)c->n_chains, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        const size_t wn = (size_t)((d[i].n + 31) / 32);
+        c->max_words = std::max(c->max_words, (int)wn);
+        c->sk_max_n = std::max(c->sk_max_n, (int)d[i].n);
+        for (int32_t r = 0; r < c->R; ++r) {
+            const size_t ch = (size_t)(i * c->R + r);
+            off_state[ch] = A.take(wn * 4);
+            off_H[ch] = A.take((size_t)d[i].n * 8);
+            off_snap[ch] = A.take(wn * (size_t)c->K * 4);
+            if (d[i].start == SG_START_GIVEN) off_given[ch] = A.take(wn * 4);
+        }
+    }
+    const size_t off_chains = A.take((size_t)c->n_chains * sizeof(SkChain));
+    const size_t off_samples = A.take((size_t)count * sizeof(SkSample));
+    const size_t off_mc = A.take((size_t)c->n_chains * sizeof(MeasureChain));
+    c->n_pairs = count * c->R * (c->R - 1) / 2;
+    const size_t off_pairs = A.take((size_t)std::max(1, c->n_pairs) * 8);
+    const size_t off_bond = A.take((size_t)c->n_chains * c->K * 8);
+    const size_t off_ovl = A.take((size_t)std::max(1, c->n_pairs) * c->K * 8);
+    const size_t off_gram = A.take((size_t)c->n_chains * c->K * c->K * 8);
+    const size_t off_acc = A.take((size_t)c->n_chains * 8);
+    const size_t off_err = A.take(8);
+    const size_t off_bondr = A.take((size_t)c->n_chains * c->K * 8);
+    const size_t off_part = A.take((size_t)count * (size_t)((c->sk_max_n + 15) / 16) * (size_t)c->R * c->K * 8);
+    c->arena_bytes = A.size;
+    c->arena = c->dev_alloc(A.size);
+    for (size_t j = 0; j < jrep.size(); ++j) {
+        const int64_t n = d[jrep[j]].n;
+        hip_check(hipMemcpy(c->at<void>(off_J[j]), d[jrep[j]].Jf, (size_t)(n * n) * 4, hipMemcpyHostToDevice));
+    }
+    c->sk.resize((size_t)c->n_chains);
+    c->sks.resize((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        SkSample sm;
+        std::memset(&sm, 0, sizeof(sm));
+        sm.Jf = c->at<float>(off_J[(size_t)jslot[(size_t)i]]);
+        sm.n = (int32_t)d[i].n;
+        sm.nch = c->R;
+        sm.chain0 = i * c->R;
+        c->sks[(size_t)i] = sm;
+        for (int32_t r = 0; r < c->R; ++r) {
+            const size_t ch = (size_t)(i * c->R + r);
+            SkChain S;
+            std::memset(&S, 0, sizeof(S));
+            S.Jf = sm.Jf;
+            S.Hd = c->at<double>(off_H[ch]);
+            S.beta = 1.0 / d[i].T;
+            S.state = c->at<uint32_t>(off_state[ch]);
+            S.snap = c->at<uint32_t>(off_snap[ch]);
+            S.accepted = c->at<unsigned long long>(off_acc) + ch;
+            S.seed = d[i].seed;
+            S.inst = d[i].instance_id;
+            S.rep = (uint32_t)r;
+            S.n = (int32_t)d[i].n;
+            S.words_n = (int32_t)((d[i].n + 31) / 32);
+            S.init_mode = d[i].start;
+            S.sample = i;
+            if (d[i].start == SG_START_GIVEN) {
+                const auto bits = pack_given(d[i].s0 + (int64_t)r * d[i].n, d[i].n, nullptr);
+                hip_check(hipMemcpy(c->at<void>(off_given[ch]), bits.data(), bits.size() * 4, hipMemcpyHostToDevice));
+                S.given = c->at<uint32_t>(off_given[ch]);
+            }
+            c->sk[ch] = S;
+        }
+    }
+    std::vector<MeasureChain> mc((size_t)c->n_chains);
+    for (int32_t ch = 0; ch < c->n_chains; ++ch)
+        mc[(size_t)ch] = MeasureChain{c->sk[(size_t)ch].snap, c->sk[(size_t)ch].words_n, c->sk[(size_t)ch].n};
+    std::vector<int32_t> pairs;
+    for (int32_t i = 0; i < count; ++i)
+        for (int32_t a = 0; a < c->R; ++a)
+            for (int32_t b = a + 1; b < c->R; ++b) {
+                pairs.push_back(i * c->R + a);
+                pairs.push_back(i * c->R + b);
+            }
+    c->sk_d = c->at<SkChain>(off_chains);
+    c->sks_d = c->at<SkSample>(off_samples);
+    c->mc_d = c->at<MeasureChain>(off_mc);
+    c->pairs_d = c->at<int32_t>(off_pairs);
+    c->bond_d = c->at<long long>(off_bond);
+    c->overlap_d = c->at<long long>(off_ovl);
+    c->gram_d = c->at<long long>(off_gram);
+    c->acc_d = c->at<unsigned long long>(off_acc);
+    c->err_d = c->at<int>(off_err);
+    c->bondr_d = c->at<double>(off_bondr);
+    c->bpart_d = c->at<double>(off_part);
+    hip_check(hipMemcpy(c->sk_d, c->sk.data(), c->sk.size() * sizeof(SkChain), hipMemcpyHostToDevice));
+    hip_check(hipMemcpy(c->sks_d, c->sks.data(), c->sks.size() * sizeof(SkSample), hipMemcpyHostToDevice));
+    hip_check(hipMemcpy(c->mc_d, mc.data(), mc.size() * sizeof(MeasureChain), hipMemcpyHostToDevice));
+    if (!pairs.empty())
+        hip_check(hipMemcpy(c->pairs_d, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
+    hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
+    hip_check(zero_i64((long long*)c->bondr_d, (size_t)c->n_chains * c->K, nullptr));
+    hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
+    hip_check(zero_i64((long long*)c->err_d, 1, nullptr));
+    c->sk_lds = skg_lds_bytes(c->sk_max_n);
+    hip_check(sk_init(c->sk_d, c->n_chains, 256, nullptr));
+    hip_check(skg_recompute(c->sks_d, count, c->sk_d, c->sk_max_n, 0, c->err_d, nullptr));
+    hip_check(hipStreamSynchronize(nullptr));
+}
+
 void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
 {
+    if (d[0].Jf) {
+        create_skg(c, d, count, o);
+        return;
+    }
     c->kind = 1;
     c->count = count;
     c->R = d[0].n_replicas;
     c->period = d[0].recompute_period ? d[0].recompute_period : 64;
     for (int32_t i = 0; i < count; ++i) {
+        if (d[i].Jf) fail(SG_EINVAL);    // a context is all real or all binary
         check_sk_desc(d[i]);
         if (d[i].n_replicas != c->R) fail(SG_EINVAL);
         if ((d[i].recompute_period ? d[i].recompute_period : 64) != c->period) fail(SG_EINVAL);
@@ -1302,6 +1631,10 @@ void enqueue_obs(sg_ctx* c, int32_t kd, long long* bond, long long* overlap, lon
     if (c->kind == 0) {
         hip_check(vb_bond(c->units_d, (int)c->units.size(), kd, bond, c->unit_chain_ids_d, K,
                           std::min(1024, c->vb_threads), c->bond_lds, s));
+        hip_check(vbm_bond(c->vbm_d, (int)c->vbm.size(), kd, bond, c->vbm_ids_d, K, s));
+    } else if (c->sk_real) {
+        hip_check(zero_i64(bond, (size_t)c->n_chains * K, s));
+        hip_check(skg_bond(c->sks_d, c->count, c->sk_d, c->sk_max_n, c->R, kd, K, c->bpart_d, c->bondr_d, s));
     } else {
         hip_check(zero_i64(bond, (size_t)c->n_chains * K, s));
         hip_check(sk_bond(c->sks_d, c->count, c->sk_d, c->sk_max_n, c->R, kd, K, bond, s));
@@ -1350,6 +1683,22 @@ void window_out(sg_ctx* c, sg_obs* out, hipStream_t s)
         hip_check(hipMemcpyAsync(out->window, c->win_d, (size_t)c->n_chains * c->kw * c->n_bins * 8,
                                  hipMemcpyDeviceToHost, s));
     if (out->window_count) window_counts(c, out->window_count);
+}
+
+// Copies the real bond sums (SK with real couplings) into sg_obs.bond_real
+// on stream s; grid times not reached yet are zeroed after the caller's
+// synchronisation (bond_real_finish).
+void bond_real_out(sg_ctx* c, sg_obs* out, hipStream_t s)
+{
+    if (!c->sk_real || !out->bond_real) return;
+    hip_check(hipMemcpyAsync(out->bond_real, c->bondr_d, (size_t)c->n_chains * c->K * 8, hipMemcpyDeviceToHost, s));
+}
+
+void bond_real_finish(sg_ctx* c, sg_obs* out, int32_t kd)
+{
+    if (!c->sk_real || !out->bond_real) return;
+    for (size_t i = 0; i < (size_t)c->n_chains * c->K; ++i)
+        if ((int32_t)(i % c->K) >= kd) out->bond_real[i] = 0.0;
 }
 
 // Status of a measurement from the context's error word.
@@ -1467,12 +1816,19 @@ sg_status sg_sweep(sg_ctx* c, int64_t n_sweeps, void* stream)
             while (left > 0) {
                 const int64_t to_check = c->period - (c->t_done % c->period);
                 const int64_t chunk = std::min(left, to_check);
-                hip_check(sk_sweep(c->sk_d, c->n_chains, c->sk_threads, c->sk_lds, c->t_done, (int32_t)chunk,
-                                   c->t_max, c->err_d, s));
+                if (c->sk_real)
+                    hip_check(skg_sweep(c->sk_d, c->n_chains, c->sk_lds, c->t_done, (int32_t)chunk, c->t_max, s));
+                else
+                    hip_check(sk_sweep(c->sk_d, c->n_chains, c->sk_threads, c->sk_lds, c->t_done, (int32_t)chunk,
+                                       c->t_max, c->err_d, s));
                 c->t_done += chunk;
                 left -= chunk;
-                if (c->t_done % c->period == 0)
-                    hip_check(sk_recompute(c->sks_d, c->count, c->sk_d, c->sk_max_n, 1, c->err_d, s));
+                if (c->t_done % c->period == 0) {
+                    if (c->sk_real)
+                        hip_check(skg_recompute(c->sks_d, c->count, c->sk_d, c->sk_max_n, 1, c->err_d, s));
+                    else
+                        hip_check(sk_recompute(c->sks_d, c->count, c->sk_d, c->sk_max_n, 1, c->err_d, s));
+                }
             }
         }
     });
@@ -1505,7 +1861,9 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
             hip_check(hipMemcpyAsync(acc.data(), c->acc_d, acc.size() * 8, hipMemcpyDeviceToHost, s));
             hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
             window_out(c, out, s);
+            bond_real_out(c, out, s);
             hip_check(hipStreamSynchronize(s));
+            bond_real_finish(c, out, kd);
             if (out->times)
                 for (int32_t k = 0; k < K; ++k) out->times[k] = c->times[(size_t)k];
             if (out->bond)
@@ -1533,8 +1891,22 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
                     st[u].resize((size_t)c->units[u].state_words);
                     hip_check(hipMemcpy(st[u].data(), c->units[u].state, st[u].size() * 4, hipMemcpyDeviceToHost));
                 }
+                std::vector<std::vector<uint64_t>> stm(c->vbm.size());
+                for (size_t u = 0; u < c->vbm.size(); ++u) {
+                    stm[u].resize((size_t)c->vbm[u].n);
+                    hip_check(hipMemcpy(stm[u].data(), c->vbm[u].state, stm[u].size() * 8, hipMemcpyDeviceToHost));
+                }
                 for (int32_t ch = 0; ch < c->n_chains; ++ch) {
                     const int32_t u = c->chain_loc[(size_t)ch].first, k = c->chain_loc[(size_t)ch].second;
+                    if (c->chain_ms[(size_t)ch]) {
+                        const int32_t i = ch / R, r = ch % R;
+                        const auto& order = c->order_of_group[(size_t)c->group_of_inst[(size_t)i]];
+                        const int32_t nn = c->vbm[(size_t)u].n;
+                        int8_t* dst = out->spins + inst_base[(size_t)i] + (int64_t)r * nn;
+                        for (int64_t p = 0; p < nn; ++p)
+                            dst[order[(size_t)p]] = ((stm[(size_t)u][(size_t)p] >> k) & 1ull) ? (int8_t)-1 : (int8_t)1;
+                        continue;
+                    }
                     const VbUnit& U = c->units[(size_t)u];
                     const int32_t i = ch / R, r = ch % R;
                     const auto& order = c->order_of_group[(size_t)c->group_of_inst[(size_t)i]];
@@ -1597,7 +1969,9 @@ sg_status sg_measure_noalloc(sg_ctx* c, sg_obs* out, void* stream)
             hip_check(hipMemcpyAsync(out->accepted, c->acc_d, (size_t)c->n_chains * 8, hipMemcpyDeviceToHost, s));
         hip_check(hipMemcpyAsync(&err_flag, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
         window_out(c, out, s);
+        bond_real_out(c, out, s);
         hip_check(hipStreamSynchronize(s));
+        bond_real_finish(c, out, kd);
         if (out->times)
             for (size_t k = 0; k < K; ++k) out->times[k] = c->times[k];
         // entries of grid times not reached hold the previous call's values
@@ -1630,6 +2004,13 @@ sg_status sg_sk_corrupt_field(sg_ctx* c, int32_t instance, int32_t replica, int6
     return guarded([&]() {
         hip_check(hipSetDevice(c->device));
         c->sync_own();
+        if (c->sk_real) {
+            double h = 0.0;
+            hip_check(hipMemcpy(&h, S.Hd + i, 8, hipMemcpyDeviceToHost));
+            h += (double)delta;
+            hip_check(hipMemcpy(S.Hd + i, &h, 8, hipMemcpyHostToDevice));
+            return;
+        }
         int32_t h = 0;
         hip_check(hipMemcpy(&h, S.H + i, 4, hipMemcpyDeviceToHost));
         h += delta;
@@ -1666,6 +2047,7 @@ sg_status sg_vb_inspect(const sg_vb_desc* d, sg_vb_tables* out)
 sg_status sg_sk_inspect(const sg_sk_desc* d, int8_t* J, uint64_t* thr)
 {
     if (!d) return SG_EINVAL;
+    if (d->Jf) return SG_EINVAL;   // binary couplings only
     return guarded([&]() {
         check_sk_desc(*d);
         const int64_t n = d->n;

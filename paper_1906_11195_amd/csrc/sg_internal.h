@@ -1,106 +1,46 @@
 // Internal device-side descriptors and kernel launchers shared by the host
-// runtime (sg_host.cpp) and the HIP kernels (sg_vb.hip, sg_sk.hip,
-// sg_measure.hip).  Not part of the public interface.
+// runtime (sg_host.cpp) and the HIP kernels (sg_vb.hip, sg_vbm.hip,
+// sg_sk.hip, sg_skg.hip, sg_measure.hip).  Not part of the public interface.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sg_vb_unit.h"
+
 namespace sg {
 
-// Device pointers stored in descriptors are generic; re-qualifying them as
-// global memory lets the compiler emit global/scalar loads, which wait only on
-// their own counters, instead of flat loads, which wait on every outstanding
-// load and LDS access.
-#define SG_G __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ SG_G T* gl(T* p)
-{
-    return (SG_G T*)p;
-}
-
-constexpr int kVbMaxChains = 8;    // chains per VB work unit
-constexpr int kVbEntPad = 8;       // zero entries after the adjacency (loads past a row stay in bounds)
-constexpr int kVbXMax = 64;        // threshold table length (max degree 63)
-constexpr int kMaxGrid = 32;       // grid times {0} U {2^k <= t_max}, t_max < 2^31
 constexpr int kSkTile = 64;        // SK decision block (one wavefront)
 constexpr int kSkThrLds = 1024;    // SK threshold entries cached in LDS
 constexpr int kWindowBinsMax = 128;  // minor-third intervals of times below 2^32
 constexpr size_t kMeasureScratchElems = (size_t)1 << 20;   // int64 staging of sg_measure_noalloc (8 MiB)
 
-// Packed spins of a VB work unit with `rpad` (1, 2, 4 or 8) chain slots,
-// "sliced" so that one 32-bit word holds P = 32 / rpad consecutive positions
-// of all rpad chains, chain c in bits [c P, c P + P) and position p at bit
-// c P + (p mod P): a word shifted right by (p mod P) has the bit of position p
-// of every chain at the bottom of that chain's field, so counting a bond for
-// all chains is a shift, an XOR and a mask.  Position p is in word p / P.
-// Bit value 1 = spin -1.
-struct VbLayout {
-    int32_t P;
-    __host__ __device__ explicit VbLayout(int32_t rpad) : P(32 / rpad) {}
-    __host__ __device__ int64_t words(int64_t n) const { return (n + P - 1) / P; }
-    __host__ __device__ int64_t word(int64_t p, int32_t) const { return p / P; }
-    __host__ __device__ int32_t bit(int64_t p, int32_t c) const { return c * P + (int32_t)(p % P); }
-};
-
-// One VB work unit = one workgroup: a graph in sweep (colour) order and up to
-// eight chains that share it.  The chains' spins live in LDS during a launch,
-// in the VbLayout packing (the same words as `state` between launches).
-struct VbUnit {
+// A multispin VB work unit (sg_vbm.hip): one graph and up to 64 chains on it,
+// each with its own couplings, temperature and random numbers, packed as the
+// bits of one 64-bit word per vertex (the paper's multispin coding: Methods;
+// SI bipartite-graph section).  The spins stay in LDS during a launch.
+constexpr int kVbmChains = 64;
+constexpr int kVbmMaxN = 16384;    // n 64-bit words must fit in LDS
+struct VbmUnit {
     const int32_t* row;        // [n+1] adjacency row starts, sweep order
-    const uint32_t* ent;       // [2m + kVbEntPad] neighbour position | (J < 0) << 31, then zeros
+    const uint32_t* ent;       // [2m + kVbEntPad] neighbour position in bits 0..30 (bit 31 ignored)
+    const uint64_t* jw;        // [2m + kVbEntPad] bit c: chain c's coupling on the entry is -1
     const int32_t* cls;        // [ncls+1] first position of each colour class
-    int32_t resident;          // 1: whole adjacency kept in LDS for the launch
-    int32_t m2;                // 2m entries
+    uint64_t* state;           // [n] spin words between launches (bit c: chain c's spin is -1)
+    const uint32_t* thr;       // [2][64][kVbXMax]: chain c's thr[x] >> 16 (0..65536), then thr[x] & 0xffff
+                               // (entry x = 0 unused)
     uint64_t key;              // Philox key (seed) shared by every chain of the unit
-    uint32_t* state;           // [state_words] packed spins between launches
-    uint32_t* snap[kVbMaxChains];       // per chain: [K][words_n] position-order bits
-    unsigned long long* accepted[kVbMaxChains];
-    uint64_t seed[kVbMaxChains];
-    uint32_t inst[kVbMaxChains];
-    uint32_t rep[kVbMaxChains];
-    uint32_t thr_hi[kVbMaxChains][kVbXMax];   // threshold >> 16 (0..65536)
-    uint32_t thr_lo[kVbMaxChains][kVbXMax];   // threshold & 0xffff
+    uint32_t* snap[kVbmChains];
+    unsigned long long* accepted[kVbmChains];
+    uint32_t inst[kVbmChains];
+    uint32_t rep[kVbmChains];
     int32_t n;
     int32_t ncls;
     int32_t nch;
-    int32_t rpad;              // bits per position: 1, 2, 4 or 8 (>= nch)
-    int32_t state_words;       // VbLayout(rpad).words(n)
     int32_t words_n;           // ceil(n / 32)
-    int32_t init_mode[kVbMaxChains];   // SG_START_* for the init kernel
-    const uint32_t* given[kVbMaxChains];   // position-order bits when GIVEN
-    // A unit split over `members` workgroups (one descriptor each, member =
-    // 0 .. members - 1): every member keeps all spins in LDS, updates its
-    // share of each colour class's chunks, writes the spin words it changed
-    // through to `state`, meets the others at a device-scope barrier (bar[0]
-    // counts arrivals within the launch, bar[1] is an abort flag; both are
-    // zeroed before every launch) and reads the class's words back.
-    int32_t members;
-    int32_t member;
-    uint32_t* bar;
-    int* err;                  // bit 2: a barrier wait timed out; bit 3: dynamic LDS not at offset 0
-    // Windowed correlation (kw > 0): the spin words at the first kw grid
-    // times (the waiting times) in the VbLayout packing, and per chain the
-    // sums of the overlap with each of them over the minor-third interval of
-    // the time each sweep ends at (see vb_window_bin).
-    uint32_t* wsnap;           // [kw][state_words]
-    long long* win[kVbMaxChains];   // per chain: [kw][n_bins]
-    int32_t kw;
-    int32_t n_bins;
+    int32_t init_mode[kVbmChains];
+    const uint32_t* given[kVbmChains];
+    uint64_t seed;
 };
-
-// Minor-third interval of time tau >= 1: m = floor(4 log2 tau) =
-// floor(log2 tau^4), from the exact 128-bit fourth power (tau < 2^32).
-__host__ __device__ __forceinline__ int32_t vb_window_bin(uint64_t tau)
-{
-    const uint64_t a = tau * tau;   // < 2^64
-#if defined(__HIP_DEVICE_COMPILE__)
-    const uint64_t hi = __umul64hi(a, a);
-#else
-    const uint64_t hi = (uint64_t)(((unsigned __int128)a * a) >> 64);
-#endif
-    const uint64_t lo = a * a;
-    return hi ? 127 - __builtin_clzll(hi) : 63 - __builtin_clzll(lo);
-}
 
 // One SK chain (a replica of an instance).
 struct SkChain {
@@ -122,6 +62,10 @@ struct SkChain {
     const uint32_t* given;     // position-order bits when GIVEN
     int32_t sample;            // index of the instance in the context
     float xslope;              // 2 beta / sqrt(N): thr[x] ~ 2^32 exp(-xslope x)
+    // real couplings (sg_skg.hip): J, J_b, J_t, H, thr unused
+    const float* Jf;           // [n][n]
+    double* Hd;                // [n] local fields between launches
+    double beta;               // 1 / T
 };
 
 // SK instance (sample) for the exact field recompute: all its chains.
@@ -131,6 +75,7 @@ struct SkSample {
     int32_t nch;
     int32_t chain0;            // index of its first chain in the chain array
     int32_t pad_;
+    const float* Jf;           // real couplings, or null
 };
 
 struct MeasureChain {
@@ -155,6 +100,17 @@ hipError_t vb_advance(int64_t* t, int32_t n_sweeps, uint32_t* bars, int n_bar, h
 size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads);
 size_t vb_resident_bytes(int32_t n, int32_t m2);
 
+// Multispin units (sg_vbm.hip).
+size_t vbm_lds_bytes(int32_t n, int threads);
+hipError_t vbm_init(const VbmUnit* units, int n_units, hipStream_t s);
+hipError_t vbm_prepare();
+hipError_t vbm_sweep(const VbmUnit* units, int n_units, int threads, size_t lds_bytes, const int64_t* t0p,
+                     int32_t n_sweeps, int64_t t_max, hipStream_t s);
+// bond sums of the snapshots of every chain of every unit: out[chain][k],
+// chain ids [unit][64]
+hipError_t vbm_bond(const VbmUnit* units, int n_units, int k_done, long long* out, const int32_t* chain_ids,
+                    int k_cap, hipStream_t s);
+
 // err_flag bit 0: recompute mismatch; bit 1: the sweep pipeline stalled.
 hipError_t sk_init(const SkChain* chains, int n_chains, int threads, hipStream_t s);
 hipError_t sk_recompute(const SkSample* samples, int n_samples, const SkChain* chains,
@@ -169,6 +125,18 @@ int sk_threads();
 // of the sk_window() blocks before it, two words each).
 int sk_tile_words();
 int sk_window();
+
+// SK with real couplings (sg_skg.hip): sweeps, direct field recomputation
+// (with `check`, error bit 0 when a field drifted by more than 1e-9 (1 + |h|))
+// and bond sums of the snapshots (partials `part` of max_samples x
+// ceil(max_n / 16) x max_nch x k_cap doubles; out[chain][k]).
+size_t skg_lds_bytes(int32_t n);
+hipError_t skg_sweep(const SkChain* chains, int n_chains, size_t lds_bytes, int64_t t0, int32_t n_sweeps,
+                     int64_t t_max, hipStream_t s);
+hipError_t skg_recompute(const SkSample* samples, int n_samples, const SkChain* chains, int max_n, int check,
+                         int* err_flag, hipStream_t s);
+hipError_t skg_bond(const SkSample* samples, int n_samples, const SkChain* chains, int max_n, int max_nch,
+                    int k_done, int k_cap, double* part, double* out, hipStream_t s);
 
 hipError_t vb_bond(const VbUnit* units, int n_units, int k_done, long long* bond_out,
                    const int32_t* unit_chain_ids, int k_cap, int threads, size_t lds_bytes,

@@ -1,0 +1,293 @@
+// Sherrington-Kirkpatrick sweeps with real couplings (Eq. 1: Gaussian J_ij
+// of variance 1/N, given as float32) on gfx950.
+//
+// The local fields h_i = sum_j J_ij s_j are real and are kept in IEEE double.
+// A flip of s_i changes every field by 2 s_i J_ij (new s_i): the product is
+// exact in double, so a field's value depends only on the order in which the
+// flips reach it, and this kernel applies them to every field in flip order,
+// as the sequential definition does.  Every `period` sweeps the fields are
+// recomputed directly (sk_recompute for real couplings below), which bounds
+// the rounding drift of the incremental sums (SI, SK section: the force is
+// the costly part and is recomputed periodically).
+//
+// Acceptance of a move with x = s_i h_i: x <= 0 accepts, else the move is
+// accepted iff r < floor(ldexp(exp(-beta (2 x)), 32)) in double, r the same
+// 32-bit uniform as for binary couplings.
+//
+// One workgroup runs one chain, visiting i = 0..N-1 in blocks of 64 spins:
+//  1. the block's 64 x 64 coupling tile is staged in LDS;
+//  2. one wavefront decides the block in rounds: every undecided lane tests
+//     its move with its current field; the first lane that accepts flips,
+//     the lanes before it keep their spins, and the lanes after it add the
+//     flip's change to their fields (from the tile) and are tested again;
+//  3. all wavefronts apply the block's flips, in order, to every field not
+//     already updated in step 2 (the fields before a flip's lane in the
+//     block and all fields outside it), streaming the flipped spins' rows.
+#include "sg_internal.h"
+#include "sg_philox.h"
+
+namespace sg {
+namespace {
+
+constexpr int kSkgThreads = 256;
+
+struct SkgLds {
+    double* H;          // [n]
+    uint32_t* bits;     // [wn + 2]
+    float* tile;        // [64][64]: rows of the block's spins, its columns
+    int32_t* flips;     // [64]: lane | (new spin -1) << 31, in flip order
+    int32_t* nflip;     // [2]
+};
+
+__device__ __forceinline__ SkgLds skg_carve(uint8_t* base, int32_t n, int32_t wn)
+{
+    SkgLds L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        uint8_t* p = base + off;
+        off += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    L.H = (double*)take((size_t)n * 8);
+    L.bits = (uint32_t*)take((size_t)(wn + 2) * 4);
+    L.tile = (float*)take(64 * 64 * 4);
+    L.flips = (int32_t*)take(64 * 4);
+    L.nflip = (int32_t*)take(16);
+    return L;
+}
+
+// 32-bit acceptance uniform of position p in sweep t (the two half-word
+// streams of the binary model, both drawn).
+__device__ __forceinline__ uint32_t skg_uniform(const SkChain* ch, uint32_t t, uint32_t p)
+{
+    const U4 A = philox_stream(ch->seed, p >> 3, t, kDomSweepHi, ch->rep, ch->inst);
+    const U4 B = philox_stream(ch->seed, p >> 3, t, kDomSweepLo, ch->rep, ch->inst);
+    return (half_word(A, p & 7u) << 16) | half_word(B, p & 7u);
+}
+
+__device__ __forceinline__ bool skg_accept(double x, double beta, uint32_t r)
+{
+    if (x <= 0.0) return true;
+    const double p = exp(-beta * (2.0 * x));
+    const uint64_t thr = (uint64_t)floor(ldexp(p, 32));
+    return (uint64_t)r < thr;
+}
+
+__global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* __restrict__ chains, int64_t t0,
+                                                                int32_t nsw, int64_t t_max)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t skg_smem[];
+    const SkChain* ch = chains + blockIdx.x;
+    const int32_t n = ch->n, wn = ch->words_n;
+    const SkgLds L = skg_carve(skg_smem, n, wn);
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    const SG_G float* __restrict__ J = gl(ch->Jf);
+    const double beta = ch->beta;
+    for (int32_t i = tid; i < n; i += nthr) L.H[i] = gl(ch->Hd)[i];
+    for (int32_t w = tid; w < wn + 2; w += nthr) L.bits[w] = w < wn ? gl(ch->state)[w] : 0u;
+    __syncthreads();
+    const int32_t NB = (n + 63) >> 6;
+    unsigned long long acc = 0;   // accepted flips (wave 0, lane 0)
+
+    for (int32_t s = 0; s < nsw; ++s) {
+        const uint32_t t = (uint32_t)(t0 + s);
+        for (int32_t b = 0; b < NB; ++b) {
+            const int32_t p0 = b << 6;
+            const int32_t m = min(64, n - p0);
+            // 1. the block's coupling tile: T[i][j] = J[p0 + i][p0 + j]
+            for (int32_t idx = tid; idx < 64 * 64; idx += nthr) {
+                const int32_t i = idx >> 6, j = idx & 63;
+                L.tile[idx] = (i < m && j < m) ? J[(int64_t)(p0 + i) * n + p0 + j] : 0.0f;
+            }
+            __syncthreads();
+            // 2. decisions (wavefront 0)
+            if (wave == 0) {
+                const bool act = lane < m;
+                const int32_t p = p0 + lane;
+                double h = act ? L.H[p] : 0.0;
+                double sp = act && ((L.bits[p >> 5] >> (p & 31)) & 1u) ? -1.0 : 1.0;
+                const uint32_t r = act ? skg_uniform(ch, t, (uint32_t)p) : 0u;
+                int32_t first = 0;   // lanes below `first` are decided
+                int32_t nf = 0;
+                for (;;) {
+                    const bool cand = act && lane >= first && skg_accept(sp * h, beta, r);
+                    const unsigned long long mk = __builtin_amdgcn_ballot_w64(cand);
+                    if (mk == 0ull) break;
+                    const int32_t i = __builtin_ctzll(mk);
+                    if (lane == i) sp = -sp;
+                    const double si = __shfl(sp, i);   // the new spin of lane i
+                    if (lane > i) h = h + (2.0 * si) * (double)L.tile[i * 64 + lane];
+                    if (lane == 0) L.flips[nf] = i | (si < 0.0 ? (int32_t)0x80000000 : 0);
+                    ++nf;
+                    first = i + 1;
+                }
+                if (act) L.H[p] = h;
+                const unsigned long long neg = __builtin_amdgcn_ballot_w64(act && sp < 0.0);
+                if (lane == 0) {
+                    L.bits[p0 >> 5] = (uint32_t)neg;
+                    if (m > 32) L.bits[(p0 >> 5) + 1] = (uint32_t)(neg >> 32);
+                    L.nflip[0] = nf;
+                    acc += (unsigned long long)nf;
+                }
+            }
+            __syncthreads();
+            // 3. the block's flips reach every other field, in flip order
+            const int32_t nf = L.nflip[0];
+            for (int32_t f = 0; f < nf; ++f) {
+                const int32_t e = L.flips[f];
+                const int32_t i = p0 + (e & 63);
+                const double a = e < 0 ? -2.0 : 2.0;
+                const SG_G float* __restrict__ row = J + (int64_t)i * n;
+                for (int32_t k = tid; k < n; k += nthr) {
+                    // fields after the flip's lane in the block were updated
+                    // when the flip was decided
+                    if (k > i && k < p0 + m) continue;
+                    L.H[k] = L.H[k] + a * (double)row[k];
+                }
+            }
+            __syncthreads();
+        }
+        const int64_t tn = t0 + s + 1;
+        if (tn <= t_max && (tn & (tn - 1)) == 0) {
+            const int k = 1 + (63 - __clzll((unsigned long long)tn));
+            for (int32_t w = tid; w < wn; w += nthr) gl(ch->snap)[(int64_t)k * wn + w] = L.bits[w];
+        }
+    }
+    for (int32_t i = tid; i < n; i += nthr) gl(ch->Hd)[i] = L.H[i];
+    for (int32_t w = tid; w < wn; w += nthr) gl(ch->state)[w] = L.bits[w];
+    if (tid == 0 && acc) atomicAdd(ch->accepted, acc);
+}
+
+// Direct fields h = J s of every chain of one sample, in a fixed order (rows
+// by wavefronts, columns strided over lanes, then a fixed butterfly), in
+// double; with `check`, a field that differs from the incremental one by more
+// than 1e-9 (1 + |h|) raises bit 0 of the error word (the rounding drift of a
+// period is many orders of magnitude below that).  grid = (row blocks of 16,
+// samples), one wavefront per block.
+__global__ void __launch_bounds__(64) skg_recompute_kernel(const SkSample* __restrict__ samples,
+                                                           const SkChain* __restrict__ chains, int check,
+                                                           int* err)
+{
+    const SkSample* sm = samples + blockIdx.y;
+    const int32_t n = sm->n;
+    const int lane = threadIdx.x;
+    const int32_t i0 = blockIdx.x * 16;
+    if (i0 >= n) return;
+    const SG_G float* __restrict__ J = gl(sm->Jf);
+    for (int32_t c = 0; c < sm->nch; ++c) {
+        const SkChain* ch = chains + sm->chain0 + c;
+        const SG_G uint32_t* st = gl(ch->state);
+        for (int32_t i = i0; i < min(n, i0 + 16); ++i) {
+            const SG_G float* row = J + (int64_t)i * n;
+            double part = 0.0;
+            for (int32_t j = lane; j < n; j += 64) {
+                const double v = (double)row[j];
+                part += ((st[j >> 5] >> (j & 31)) & 1u) ? -v : v;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+            if (lane == 0) {
+                const double old = ch->Hd[i];
+                if (check && fabs(old - part) > 1e-9 * (1.0 + fabs(part))) atomicOr(err, 1);
+                ch->Hd[i] = part;
+            }
+        }
+    }
+}
+
+// Bond sums B = (1/2) sum_i s_i (J s)_i of every snapshot (chain c, grid time
+// k) of one sample, in double and in a fixed order: each wavefront forms
+// partial sums over 16 rows, written to part[sample][row block][column], then
+// skg_bond_reduce adds the row blocks in order.  grid = (row blocks of 16,
+// samples).
+__global__ void __launch_bounds__(64) skg_bond_kernel(const SkSample* __restrict__ samples,
+                                                      const SkChain* __restrict__ chains, int kd, int nrb,
+                                                      int ncol_cap, double* __restrict__ part)
+{
+    const SkSample* sm = samples + blockIdx.y;
+    const int32_t n = sm->n;
+    const int lane = threadIdx.x;
+    const int32_t i0 = blockIdx.x * 16;
+    if (i0 >= n) return;
+    const SG_G float* __restrict__ J = gl(sm->Jf);
+    const int32_t ncol = sm->nch * kd;
+    for (int32_t col = 0; col < ncol; ++col) {
+        const SkChain* ch = chains + sm->chain0 + col / kd;
+        const int32_t k = col % kd;
+        const SG_G uint32_t* sn = gl(ch->snap) + (int64_t)k * ch->words_n;
+        double acc = 0.0;
+        for (int32_t i = i0; i < min(n, i0 + 16); ++i) {
+            const SG_G float* row = J + (int64_t)i * n;
+            double d = 0.0;
+            for (int32_t j = lane; j < n; j += 64) {
+                const double v = (double)row[j];
+                d += ((sn[j >> 5] >> (j & 31)) & 1u) ? -v : v;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o);
+            acc += ((sn[i >> 5] >> (i & 31)) & 1u) ? -d : d;
+        }
+        if (lane == 0) part[((int64_t)blockIdx.y * nrb + blockIdx.x) * ncol_cap + col] = acc;
+    }
+}
+
+// out[chain][k] = (1/2) sum over row blocks (in order) of the partial sums.
+__global__ void skg_bond_reduce(const SkSample* __restrict__ samples, int n_samples, int kd, int nrb,
+                                int ncol_cap, int k_cap, const double* __restrict__ part,
+                                double* __restrict__ out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_samples * ncol_cap) return;
+    const int32_t smp = (int32_t)(idx / ncol_cap), col = (int32_t)(idx % ncol_cap);
+    const SkSample* sm = samples + smp;
+    if (col >= sm->nch * kd) return;
+    const int32_t rbs = (sm->n + 15) / 16;
+    double s = 0.0;
+    for (int32_t rb = 0; rb < rbs; ++rb) s += part[((int64_t)smp * nrb + rb) * ncol_cap + col];
+    out[(int64_t)(sm->chain0 + col / kd) * k_cap + col % kd] = 0.5 * s;
+}
+
+}  // namespace
+
+size_t skg_lds_bytes(int32_t n)
+{
+    const size_t wn = (size_t)(n + 31) / 32;
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    return r16((size_t)n * 8) + r16((wn + 2) * 4) + 64 * 64 * 4 + 64 * 4 + 16;
+}
+
+hipError_t skg_sweep(const SkChain* chains, int n_chains, size_t lds_bytes, int64_t t0, int32_t n_sweeps,
+                     int64_t t_max, hipStream_t s)
+{
+    if (n_chains <= 0 || n_sweeps <= 0) return hipSuccess;
+    static const hipError_t attr = hipFuncSetAttribute((const void*)skg_sweep_kernel,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(skg_sweep_kernel, dim3(n_chains), dim3(kSkgThreads), lds_bytes, s, chains, t0, n_sweeps,
+                       t_max);
+    return hipGetLastError();
+}
+
+hipError_t skg_recompute(const SkSample* samples, int n_samples, const SkChain* chains, int max_n, int check,
+                         int* err_flag, hipStream_t s)
+{
+    if (n_samples <= 0) return hipSuccess;
+    hipLaunchKernelGGL(skg_recompute_kernel, dim3((max_n + 15) / 16, n_samples), dim3(64), 0, s, samples, chains,
+                       check, err_flag);
+    return hipGetLastError();
+}
+
+hipError_t skg_bond(const SkSample* samples, int n_samples, const SkChain* chains, int max_n, int max_nch,
+                    int k_done, int k_cap, double* part, double* out, hipStream_t s)
+{
+    if (n_samples <= 0 || k_done <= 0) return hipSuccess;
+    const int nrb = (max_n + 15) / 16, ncol_cap = max_nch * k_cap;
+    hipLaunchKernelGGL(skg_bond_kernel, dim3(nrb, n_samples), dim3(64), 0, s, samples, chains, k_done, nrb,
+                       ncol_cap, part);
+    const int64_t tot = (int64_t)n_samples * ncol_cap;
+    hipLaunchKernelGGL(skg_bond_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, samples, n_samples,
+                       k_done, nrb, ncol_cap, k_cap, part, out);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -486,47 +486,107 @@ __device__ void vb_snapshot(const VbUnit* __restrict__ up, const uint32_t* __res
 // (mod members * threads): the members of a split unit count disjoint words
 // and no thread reads another's stores.
 template <int RPAD>
+__device__ __forceinline__ void win_count(uint32_t* cnt, uint32_t d, int32_t nch)
+{
+    using S = Sl<RPAD>;
+#pragma unroll
+    for (int c = 0; c < RPAD; ++c)
+        if (c < nch)
+            cnt[c] += (uint32_t)__popc(d & (S::P == 32 ? 0xffffffffu : (((1u << (S::P & 31)) - 1u) << (c * S::P))));
+}
+
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+template <int RPAD>
+__device__ __forceinline__ void win_count4(uint32_t* cnt, v4u a, v4u b, int32_t nch)
+{
+    const v4u d = a ^ b;
+    win_count<RPAD>(cnt, d.x, nch);
+    win_count<RPAD>(cnt, d.y, nch);
+    win_count<RPAD>(cnt, d.z, nch);
+    win_count<RPAD>(cnt, d.w, nch);
+}
+
+// Windowed correlation (the paper's estimator: C(t_w + t, t_w) averaged over
+// minor-third intervals of t_w + t, ratio 2^(1/4); Results and discussion,
+// and the SI section on the extrapolation to large sizes and times), at the
+// end of the sweep that ends at time tau <= t_max: for every stored waiting
+// time t_w < tau and every chain, the overlap sum_i s_i(tau) s_i(t_w) =
+// n - 2 popcount(s(tau) xor s(t_w)) over the chain's fields, added to the
+// chain's sum for the interval of tau.  The spin words at the waiting times
+// are stored in the same sliced packing as the LDS words (rows of `ws4`
+// 16-byte groups; the words past state_words are zero on both sides), so one
+// XOR and a masked popcount per word and chain count every chain.  The
+// stored words are streamed from HBM with 16-byte loads, four groups of two
+// waiting times in flight per lane.  Each thread counts (and, at the waiting
+// times, stores) the groups i = tid + member * threads (mod members *
+// threads): the members of a split unit count disjoint words and no thread
+// reads another's stores.
+template <int RPAD>
 __device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ up, uint32_t sp_off,
                                                    uint32_t acc_off, int64_t tau, int32_t k_store)
 {
-    using S = Sl<RPAD>;
+    constexpr int U = 4;
+    typedef __attribute__((address_space(3))) v4u lds_u4;
     typedef __attribute__((address_space(3))) uint32_t lds_u32;
-    const lds_u32* sp = (const lds_u32*)(size_t)sp_off;
+    const lds_u4* sp4 = (const lds_u4*)(size_t)sp_off;
     lds_u32* wacc = (lds_u32*)(size_t)acc_off;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int32_t sw = up->state_words, nch = up->nch;
+    const int32_t nch = up->nch;
+    const int32_t sw4 = (up->state_words + 3) >> 2;
     // waiting times before tau: t_w = 0, and t_w = 2^(k-1) < tau for k >= 1
     const int32_t kv = min(up->kw, tau >= 2 ? 2 + (63 - __clzll((unsigned long long)(tau - 1))) : 1);
     const int32_t stride = nthr * up->members;
     const int32_t w0 = tid + up->member * nthr;
-    SG_G uint32_t* ws = gl(up->wsnap);
+    SG_G v4u* ws4 = (SG_G v4u*)gl(up->wsnap);
     for (int i = tid; i < kv * RPAD; i += nthr) wacc[i] = 0u;
     __syncthreads();
-    for (int32_t k = 0; k < kv; ++k) {
-        uint32_t cnt[RPAD];
+    const v4u zero = {0u, 0u, 0u, 0u};
+    for (int32_t k = 0; k < kv; k += 2) {
+        const bool two = k + 1 < kv;
+        const SG_G v4u* r0 = ws4 + (int64_t)k * sw4;
+        const SG_G v4u* r1 = ws4 + (int64_t)(two ? k + 1 : k) * sw4;
+        uint32_t c0[RPAD], c1[RPAD];
 #pragma unroll
-        for (int c = 0; c < RPAD; ++c) cnt[c] = 0u;
-        const SG_G uint32_t* wk = ws + (int64_t)k * sw;
-        for (int32_t w = w0; w < sw; w += stride) {
-            const uint32_t d = sp[w] ^ wk[w];
+        for (int c = 0; c < RPAD; ++c) {
+            c0[c] = 0u;
+            c1[c] = 0u;
+        }
+        for (int32_t i0 = w0; i0 < sw4; i0 += U * stride) {
+            v4u a[U], b0[U], b1[U];
 #pragma unroll
-            for (int c = 0; c < RPAD; ++c)
-                if (c < nch)
-                    cnt[c] += (uint32_t)__popc(d & (S::P == 32 ? 0xffffffffu : (((1u << (S::P & 31)) - 1u) << (c * S::P))));
+            for (int u = 0; u < U; ++u) {
+                const int32_t i = i0 + u * stride;
+                const bool ok = i < sw4;
+                b0[u] = ok ? r0[i] : zero;
+                b1[u] = ok && two ? r1[i] : zero;
+                a[u] = ok ? sp4[i] : zero;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                win_count4<RPAD>(c0, a[u], b0[u], nch);
+                if (two) win_count4<RPAD>(c1, a[u], b1[u], nch);
+            }
         }
 #pragma unroll
         for (int c = 0; c < RPAD; ++c) {
             if (c < nch) {
-                uint32_t v = cnt[c];
+                uint32_t v0 = c0[c], v1 = c1[c];
 #pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
-                if ((tid & 63) == 0 && v) atomicAdd((uint32_t*)&wacc[k * RPAD + c], v);
+                for (int o = 32; o >= 1; o >>= 1) {
+                    v0 += (uint32_t)__shfl_xor((int)v0, o);
+                    v1 += (uint32_t)__shfl_xor((int)v1, o);
+                }
+                if ((tid & 63) == 0) {
+                    if (v0) atomicAdd((uint32_t*)&wacc[k * RPAD + c], v0);
+                    if (two && v1) atomicAdd((uint32_t*)&wacc[(k + 1) * RPAD + c], v1);
+                }
             }
         }
     }
     if (k_store >= 0) {
-        SG_G uint32_t* dst = ws + (int64_t)k_store * sw;
-        for (int32_t w = w0; w < sw; w += stride) dst[w] = sp[w];
+        SG_G v4u* dst = ws4 + (int64_t)k_store * sw4;
+        for (int32_t i = w0; i < sw4; i += stride) dst[i] = sp4[i];
     }
     __syncthreads();
     const int32_t bin = vb_window_bin((uint64_t)tau);
@@ -566,6 +626,7 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
 
     const SG_G uint32_t* gstate = gl(up->state);
     for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = gstate[w];
+    if (tid < ((sw + 3) & ~3) - sw) L.sp[sw + tid] = 0u;   // pad to 16 bytes (read by vb_window)
     // chain c's threshold high halves: word c kTab + j holds the entry for
     // x = 64 - j (0x10000 for x <= 0: always accepted)
     for (int i = tid; i < kVbMaxChains * kTab; i += nthr) {

@@ -1,0 +1,388 @@
+// Viana-Bray sweeps in the paper's multispin coding (Methods; SI section on
+// the bipartite random regular graph): up to 64 chains that share one graph,
+// each with its own couplings, temperature and random numbers, are the 64
+// bits of one word per vertex.  The chains are those of the per-chain layout
+// (sg_vb.hip), with the same colour-class sweep and the same random streams,
+// so every trajectory is identical; only the data layout differs.
+//
+// One workgroup owns one unit and keeps its n spin words in LDS for the whole
+// launch.  A colour class is cut into aligned chunks of 64 positions;
+// wavefront w takes chunks w, w + W, ..., lane i position 64 b + i.  For
+// every neighbour the lane XORs the neighbour's word, its own word and the
+// edge's coupling word: bit c is set where chain c's bond is unsatisfied, and
+// a bit-sliced counter (4 bit planes, 6 when a degree in the chunk exceeds
+// 15) counts them for all 64 chains at once.  The decisions are then taken
+// chain by chain: the counts of 8 chains are gathered into one word of
+// nibbles, x = deg - 2 count indexes the chain's threshold table (high 16
+// bits, 65536 for x <= 0), and the high half-word A of the chain's uniform is
+// compared with it; a tie (probability 2^-16) is settled on the low halves as
+// in the per-chain layout.  The Philox blocks of 8 chains are drawn per pass,
+// one per lane, and exchanged through LDS.  Each lane owns its position's
+// word, so the flips are written back with a plain XOR.
+#include "sg_internal.h"
+#include "sg_philox.h"
+
+namespace sg {
+namespace {
+
+constexpr int kMaxClsM = 64;   // colour classes (degree <= 63)
+constexpr int kThrSpan = 32;   // LDS threshold entries per chain: x = -15 .. 15 (index x + 16)
+
+__device__ __forceinline__ void wave_sync_m()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct VbmLds {
+    uint64_t* sp;                 // [n] spin words
+    uint32_t* thr;                // [64][kThrSpan]: chain c, x + 16 -> thr[x] >> 16; 65536 for x <= 0
+    uint32_t* ri;                 // [64][2]: replica, instance
+    int32_t* cls;                 // [kMaxClsM + 4]
+    unsigned long long* acc;      // [64] accepted flips of the launch
+    uint4* xch;                   // [waves][64] Philox blocks of 8 chains
+};
+
+__device__ __forceinline__ VbmLds vbm_carve(uint8_t* base, int32_t n, int waves)
+{
+    VbmLds L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        uint8_t* p = base + off;
+        off += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    L.sp = (uint64_t*)take((size_t)n * 8);
+    L.thr = (uint32_t*)take((size_t)kVbmChains * kThrSpan * 4);
+    L.ri = (uint32_t*)take((size_t)kVbmChains * 8);
+    L.cls = (int32_t*)take((size_t)(kMaxClsM + 4) * 4);
+    L.acc = (unsigned long long*)take((size_t)kVbmChains * 8);
+    L.xch = (uint4*)take((size_t)waves * 64 * 16);
+    return L;
+}
+
+// bit i (i < 8) of x -> bit 4 i
+__device__ __forceinline__ uint32_t spread8(uint32_t x)
+{
+    x &= 0xffu;
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x;
+}
+
+// Counts of chains 8 i .. 8 i + 7 as nibbles (chain 8 i + j at bits 4 j).
+__device__ __forceinline__ uint32_t nibbles(const uint64_t* pl, int i)
+{
+    const int sh = 8 * i;
+    return spread8((uint32_t)(pl[0] >> sh)) | (spread8((uint32_t)(pl[1] >> sh)) << 1) |
+           (spread8((uint32_t)(pl[2] >> sh)) << 2) | (spread8((uint32_t)(pl[3] >> sh)) << 3);
+}
+
+// Count of chain c from np bit planes.
+__device__ __forceinline__ int32_t count_of(const uint64_t* pl, int np, int c)
+{
+    int32_t u = 0;
+    for (int k = 0; k < np; ++k) u |= (int32_t)((pl[k] >> c) & 1ull) << k;
+    return u;
+}
+
+__global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restrict__ units,
+                                                         const int64_t* __restrict__ t0p, int32_t nsw,
+                                                         int64_t t_max)
+{
+    extern __shared__ __attribute__((aligned(16))) uint8_t vbm_smem[];
+    const VbmUnit* up = (const VbmUnit*)(gl(units) + blockIdx.x);
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
+    const int W = nthr >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int32_t n = up->n, nch = up->nch, ncls = up->ncls, wn = up->words_n;
+    const VbmLds L = vbm_carve(vbm_smem, n, W);
+    const SG_G uint64_t* gstate = gl(up->state);
+    for (int32_t i = tid; i < n; i += nthr) L.sp[i] = gstate[i];
+    const SG_G uint32_t* gthr = gl(up->thr);
+    for (int i = tid; i < kVbmChains * kThrSpan; i += nthr) {
+        const int c = i / kThrSpan, x = i - c * kThrSpan - 16;
+        L.thr[i] = x <= 0 ? 0x10000u : (c < nch ? gthr[c * kVbXMax + x] : 0u);
+    }
+    if (tid < kVbmChains) {
+        L.ri[2 * tid] = up->rep[tid];
+        L.ri[2 * tid + 1] = up->inst[tid];
+        L.acc[tid] = 0ull;
+    }
+    for (int32_t k = tid; k <= ncls; k += nthr) L.cls[k] = gl(up->cls)[k];
+    __syncthreads();
+    const int64_t t0 = *gl(t0p);
+    const uint64_t key = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(up->key >> 32)) << 32) |
+                         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)up->key);
+    const SG_G int32_t* __restrict__ row = gl(up->row);
+    const SG_G uint32_t* __restrict__ ent = gl(up->ent);
+    const SG_G uint64_t* __restrict__ jw = gl(up->jw);
+    const uint32_t* xw = (const uint32_t*)(L.xch + wave * 64);
+    const char* thb = (const char*)L.thr;
+
+    for (int32_t s = 0; s < nsw; ++s) {
+        const uint32_t t = (uint32_t)(t0 + s);
+        // accepted flips of this sweep, per chain, in 8 bit planes (a lane
+        // takes at most 255 chunks per sweep: threads >= 128, n <= 16384)
+        uint64_t ap[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ap[k] = 0ull;
+        for (int32_t k = 0; k < ncls; ++k) {
+            const int32_t lo = __builtin_amdgcn_readfirstlane(L.cls[k]);
+            const int32_t hi = __builtin_amdgcn_readfirstlane(L.cls[k + 1]);
+            const int32_t nck = hi > lo ? ((hi - 1) >> 6) - (lo >> 6) + 1 : 0;
+            for (int32_t j = wave; j < nck; j += W) {
+                const int32_t qb = ((lo >> 6) + j) << 6;
+                const int32_t q = qb + lane;
+                const bool act = q >= lo && q < hi;
+                const int32_t r0 = act ? row[q] : 0;
+                const int32_t d = act ? row[q + 1] - r0 : 0;
+                const uint64_t own = act ? L.sp[q] : 0ull;
+                const bool wide = __any(d > 15);
+                uint64_t pl[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+                for (int32_t e = 0; __any(e < d); ++e) {
+                    if (e < d) {
+                        const uint32_t en = ent[r0 + e] & 0x7fffffffu;
+                        const uint64_t u = L.sp[en] ^ own ^ jw[r0 + e];
+                        // add one bit per chain to the bit-sliced counter
+                        uint64_t cy = u;
+#pragma unroll
+                        for (int b = 0; b < 6; ++b) {
+                            if (b >= 4 && !wide) break;
+                            const uint64_t nc = pl[b] & cy;
+                            pl[b] ^= cy;
+                            cy = nc;
+                        }
+                    }
+                }
+                // decisions, 8 chains per Philox pass
+                uint64_t A = 0ull, tie = 0ull;
+                const uint32_t tb = (uint32_t)(16 + d) * 4u;   // byte offset of x = d in a chain's table
+                for (int i = 0; i < 8; ++i) {
+                    if (8 * i >= nch) break;
+                    {
+                        const int cc = 8 * i + (lane >> 3);
+                        const int ce = cc < nch ? cc : 0;
+                        const U4 B = philox_stream(key, ((uint32_t)qb >> 3) + (uint32_t)(lane & 7), t, kDomSweepHi,
+                                                   L.ri[2 * ce], L.ri[2 * ce + 1]);
+                        L.xch[wave * 64 + lane] = make_uint4(B.x, B.y, B.z, B.w);
+                    }
+                    wave_sync_m();
+                    const uint32_t nw = wide ? 0u : nibbles(pl, i);
+#pragma unroll
+                    for (int c8 = 0; c8 < 8; ++c8) {
+                        const int c = 8 * i + c8;
+                        if (c >= nch) break;
+                        const uint32_t rw = xw[(c8 * 8 + (lane >> 3)) * 4 + ((lane & 7) >> 1)];
+                        const uint32_t rh = (rw >> (16 * (lane & 1))) & 0xffffu;
+                        uint32_t th;
+                        if (!wide) {
+                            const uint32_t u = (nw >> (4 * c8)) & 0xfu;
+                            th = *(const uint32_t*)(thb + (c * kThrSpan * 4) + (tb - 8u * u));
+                        } else {
+                            const int32_t x = d - 2 * count_of(pl, 6, c);
+                            th = x <= 0 ? 0x10000u : gthr[c * kVbXMax + x];
+                        }
+                        A |= (uint64_t)(rh < th) << c;
+                        tie |= (uint64_t)(rh == th) << c;
+                    }
+                    wave_sync_m();
+                }
+                if (!act) {
+                    A = 0ull;
+                    tie = 0ull;
+                }
+                if (__any(tie != 0ull)) {
+                    // A equals the high half of the threshold: decide on the
+                    // low halves (second stream)
+                    uint64_t tm = tie;
+                    while (tm) {
+                        const int c = __builtin_ctzll(tm);
+                        tm &= tm - 1ull;
+                        const int32_t x = d - 2 * count_of(pl, wide ? 6 : 4, c);
+                        const U4 Bl = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, L.ri[2 * c], L.ri[2 * c + 1]);
+                        if (half_word(Bl, (uint32_t)q & 7u) < gthr[kVbmChains * kVbXMax + c * kVbXMax + x]) A |= 1ull << c;
+                    }
+                }
+                if (act) L.sp[q] = own ^ A;
+                // count the accepted flips in the bit-sliced counter
+                uint64_t cy = A;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const uint64_t nc = ap[b] & cy;
+                    ap[b] ^= cy;
+                    cy = nc;
+                }
+            }
+            __syncthreads();
+        }
+        // flush the sweep's accepted counts: per chain, the wavefront's sum
+#pragma unroll 1
+        for (int c = 0; c < nch; ++c) {
+            unsigned long long tot = 0ull;
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                tot += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(((ap[b] >> c) & 1ull) != 0ull)) << b;
+            if (lane == 0 && tot) atomicAdd(&L.acc[c], tot);
+        }
+        const int64_t tn = t0 + s + 1;
+        if (tn <= t_max && (tn & (tn - 1)) == 0) {
+            const int kk = 1 + (63 - __clzll((unsigned long long)tn));
+            for (int32_t idx = tid; idx < nch * wn; idx += nthr) {
+                const int32_t c = idx / wn, w = idx - c * wn;
+                uint32_t bits = 0u;
+                for (int b = 0; b < 32; ++b) {
+                    const int32_t p = 32 * w + b;
+                    if (p < n) bits |= (uint32_t)((L.sp[p] >> c) & 1ull) << b;
+                }
+                gl(up->snap[c])[(int64_t)kk * wn + w] = bits;
+            }
+            __syncthreads();
+        }
+    }
+    for (int32_t i = tid; i < n; i += nthr) gl(up->state)[i] = L.sp[i];
+    __syncthreads();
+    if (tid < nch && L.acc[tid]) atomicAdd(up->accepted[tid], L.acc[tid]);
+}
+
+// Initial configurations (the per-chain definition: chain c's start bits in
+// position order) and the t = 0 snapshots.
+__global__ void __launch_bounds__(256) vbm_init_kernel(const VbmUnit* __restrict__ units)
+{
+    const VbmUnit* up = units + blockIdx.x;
+    const int32_t n = up->n, wn = up->words_n, nch = up->nch;
+    for (int32_t idx = threadIdx.x; idx < nch * wn; idx += blockDim.x) {
+        const int32_t c = idx / wn, w = idx - c * wn;
+        uint32_t bits;
+        if (up->init_mode[c] == 0) {
+            const U4 o = philox_stream(up->seed, (uint32_t)(w >> 2), 0u, kDomInit, up->rep[c], up->inst[c]);
+            bits = word_of(o, (uint32_t)(w & 3));
+        } else if (up->init_mode[c] == 1) {
+            bits = 0u;
+        } else {
+            bits = up->given[c][w];
+        }
+        const int32_t pe = n - 32 * w;
+        if (pe < 32) bits &= (1u << pe) - 1u;
+        up->snap[c][w] = bits;
+    }
+    __syncthreads();
+    for (int32_t p = threadIdx.x; p < n; p += blockDim.x) {
+        uint64_t word = 0ull;
+        for (int32_t c = 0; c < nch; ++c) word |= (uint64_t)((up->snap[c][p >> 5] >> (p & 31)) & 1u) << c;
+        up->state[p] = word;
+    }
+}
+
+// Bond sums of every chain's snapshot k.  The chains' position-order
+// snapshot words are transposed into one 64-bit word per position by wave
+// ballots (lane c holds chain c's word of 32 positions), then every directed
+// adjacency entry gives the unsatisfied bonds of all chains as one XOR,
+// counted in a bit-sliced counter per thread.  Each edge is two directed
+// entries, so per chain B = (entries - 2 unsatisfied entries) / 2.
+// grid = (units, k_done), 256 threads, n 64-bit words of dynamic LDS.
+__global__ void __launch_bounds__(256) vbm_bond_kernel(const VbmUnit* __restrict__ units,
+                                                       const int32_t* __restrict__ chain_ids, int k_cap,
+                                                       long long* __restrict__ out)
+{
+    extern __shared__ __attribute__((aligned(16))) uint64_t bw[];
+    __shared__ unsigned long long uns[kVbmChains];
+    __shared__ unsigned long long ents;
+    const VbmUnit* up = units + blockIdx.x;
+    const int k = blockIdx.y;
+    const int32_t n = up->n, wn = up->words_n, nch = up->nch;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
+    if (tid < kVbmChains) uns[tid] = 0ull;
+    if (tid == 0) ents = 0ull;
+    for (int32_t w = wave; w < wn; w += W) {
+        const uint32_t word = lane < nch ? up->snap[lane][(int64_t)k * wn + w] : 0u;
+        for (int b = 0; b < 32; ++b) {
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(((word >> b) & 1u) != 0u);
+            if (lane == b && 32 * w + b < n) bw[32 * w + b] = m;
+        }
+    }
+    __syncthreads();
+    uint64_t pl[12];
+#pragma unroll
+    for (int b = 0; b < 12; ++b) pl[b] = 0ull;
+    uint32_t e_cnt = 0;
+    for (int32_t p = tid; p < n; p += blockDim.x) {
+        const uint64_t wp = bw[p];
+        const int32_t e1 = up->row[p + 1];
+        for (int32_t e = up->row[p]; e < e1; ++e) {
+            const int32_t q = (int32_t)(up->ent[e] & 0x7fffffffu);
+            uint64_t cy = wp ^ bw[q] ^ up->jw[e];
+#pragma unroll
+            for (int b = 0; b < 12; ++b) {
+                const uint64_t nc = pl[b] & cy;
+                pl[b] ^= cy;
+                cy = nc;
+            }
+            ++e_cnt;
+        }
+    }
+    // per chain: the workgroup's unsatisfied directed entries
+    for (int c = 0; c < nch; ++c) {
+        unsigned long long tot = 0ull;
+#pragma unroll
+        for (int b = 0; b < 12; ++b)
+            tot += (unsigned long long)__popcll(__builtin_amdgcn_ballot_w64(((pl[b] >> c) & 1ull) != 0ull)) << b;
+        if (lane == 0 && tot) atomicAdd(&uns[c], tot);
+    }
+    unsigned long long et = e_cnt;
+    for (int o = 32; o >= 1; o >>= 1) et += __shfl_xor(et, o);
+    if (lane == 0 && et) atomicAdd(&ents, et);
+    __syncthreads();
+    if (tid < nch)
+        out[(int64_t)chain_ids[blockIdx.x * kVbmChains + tid] * k_cap + k] =
+            ((long long)ents - 2ll * (long long)uns[tid]) / 2;
+}
+
+}  // namespace
+
+size_t vbm_lds_bytes(int32_t n, int threads)
+{
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    return r16((size_t)n * 8) + r16((size_t)kVbmChains * kThrSpan * 4) + r16((size_t)kVbmChains * 8) +
+           r16((size_t)(kMaxClsM + 4) * 4) + r16((size_t)kVbmChains * 8) + (size_t)(threads / 64) * 64 * 16;
+}
+
+hipError_t vbm_init(const VbmUnit* units, int n_units, hipStream_t s)
+{
+    if (n_units <= 0) return hipSuccess;
+    hipLaunchKernelGGL(vbm_init_kernel, dim3(n_units), dim3(256), 0, s, units);
+    return hipGetLastError();
+}
+
+hipError_t vbm_prepare()
+{
+    static const hipError_t a1 = hipFuncSetAttribute((const void*)vbm_sweep_kernel,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (a1 != hipSuccess) return a1;
+    static const hipError_t a2 = hipFuncSetAttribute((const void*)vbm_bond_kernel,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    return a2;
+}
+
+hipError_t vbm_sweep(const VbmUnit* units, int n_units, int threads, size_t lds_bytes, const int64_t* t0p,
+                     int32_t n_sweeps, int64_t t_max, hipStream_t s)
+{
+    if (n_units <= 0 || n_sweeps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(vbm_sweep_kernel, dim3(n_units), dim3(threads), lds_bytes, s, units, t0p, n_sweeps,
+                       t_max);
+    return hipGetLastError();
+}
+
+hipError_t vbm_bond(const VbmUnit* units, int n_units, int k_done, long long* out, const int32_t* chain_ids,
+                    int k_cap, hipStream_t s)
+{
+    if (n_units <= 0 || k_done <= 0) return hipSuccess;
+    // one 64-bit word per position of the largest unit (n <= kVbmMaxN)
+    hipLaunchKernelGGL(vbm_bond_kernel, dim3(n_units, k_done), dim3(256), (size_t)kVbmMaxN * 8, s, units,
+                       chain_ids, k_cap, out);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -70,6 +70,30 @@ def vb_uneven(count: int = 1024, lo: int = 10, hi: int = 20, temps=(0.6, 0.8, 1.
     return out
 
 
+def gaussian_couplings(n: int, seed: int) -> np.ndarray:
+    """SK couplings of the main text (Eq. 1): J_ij = J_ji Gaussian with mean 0
+    and variance 1/N, J_ii = 0, as float32 [n, n]: numpy default_rng(seed)
+    float32 standard normals (row by row; the upper triangle is used) times
+    float32(1 / sqrt(N)), mirrored to the lower triangle."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n, n), dtype=np.float32)
+    J = np.triu(z, 1)
+    J *= np.float32(1.0 / np.sqrt(float(n)))
+    J += J.T
+    return J
+
+
+def sk_gaussian_batch(n_samples: int = 64, n: int = 4096, T: float = 0.5, seed: int = 7):
+    """SK with Gaussian couplings: (descriptors, coupling matrices), one matrix
+    per sample, 2 replicas each."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        Js = list(ex.map(lambda s: gaussian_couplings(n, seed * 1000003 + s), range(n_samples)))
+    descs = [SkDesc(n=n, T=T, seed=seed, instance_id=s, graph_id=s, n_replicas=2, recompute_period=64,
+                    Jf=Js[s]) for s in range(n_samples)]
+    return descs, Js
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
