@@ -358,6 +358,56 @@ def run_rrbg(args, torch, sg, workloads):
                               achieved=round(byts / el / 1e9, 1), bytes_per_update=round(byts / upd, 3)))
 
 
+def run_multispin(args, torch, sg, workloads):
+    """The paper's multispin workload (Methods; SI bipartite-graph section):
+    96 random regular bipartite graphs (degree 4, N = 16384), 32 coupling
+    samples x 2 replicas on each = 6144 chains, T cycling over {0.6, 0.8,
+    1.2}.  Run in the multispin layout (64 chains of a graph per 64-bit word)
+    and in the per-chain layout (each sample's two replicas share one unit),
+    same sweeps, both timed."""
+    t0 = time.perf_counter()
+    descs = workloads.vb_multispin_batched()
+    gen_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    S = args.multispin_sweeps
+    out = dict(workload="VB multispin: 96 RRBG graphs (degree 4, N=16384) x 32 coupling samples x 2 replicas "
+                        "= 6144 chains, T{0.6,0.8,1.2}; sweeps 16..%d" % (16 + S), generate_s=round(gen_s, 2))
+    n_total = sum(d.n for d in descs) * 2
+    res = {}
+    for name, ms in (("multispin", True), ("per_chain", False)):
+        t0 = time.perf_counter()
+        ctx = sg.sg_create_vb(descs, t_max=workloads.VB_BATCHED_SWEEPS, multispin=ms)
+        create_s = time.perf_counter() - t0
+        sg.sg_sweep(ctx, 16, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        sg.sg_sweep(ctx, S, stream)
+        e1.record(stream)
+        r = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sg.sg_free(ctx)
+        dev_s = e0.elapsed_time(e1) * 1e-3
+        res[name] = r
+        out[name] = dict(updates_per_ns=n_total * S / (el * 1e9), sweep_kernel_updates_per_ns=n_total * S / (dev_s * 1e9),
+                         create_s=round(create_s, 2))
+    # bytes per chain-update by the scope table's model, r chains sharing the
+    # graph stream, plus the per-chain couplings the multispin layout reads
+    # with it (one bit per chain and adjacency entry: c / 8 B)
+    bpu_ms = (4 * 4 + 4) / 64 + 0.25 + 4 / 8
+    bpu_pc = (4 * 4 + 4) / 2 + 0.25
+    for name, bpu in (("multispin", bpu_ms), ("per_chain", bpu_pc)):
+        rate = out[name]["sweep_kernel_updates_per_ns"] * 1e9
+        out[name]["roofline"] = dict(bound="hbm", bytes_per_update=round(bpu, 3), achieved=round(rate * bpu / 1e9, 1),
+                                     unit="GB/s", frac=round(rate * bpu / HBM_PEAK_BPS, 4))
+    out["identical"] = bool(all(np.array_equal(res["multispin"][k], res["per_chain"][k])
+                                for k in ("bond", "gram", "accepted", "overlap")))
+    out["speedup"] = round(out["multispin"]["updates_per_ns"] / out["per_chain"]["updates_per_ns"], 3)
+    return out
+
+
 def run_window(args, torch, sg, workloads):
     """The batched configuration with the paper's windowed estimator of C
     (SG_OPT_WINDOW, waiting times 0, 1, 2, 4, .., 2^12): after every sweep
@@ -547,9 +597,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-vb", action="store_true", help="the batched VB leg only (same as --legs vb)")
-    ap.add_argument("--legs", default="vb,plain,sk,sk_gauss,uneven,rrbg,window,serving,serving_full",
+    ap.add_argument("--legs", default="vb,plain,sk,sk_gauss,uneven,rrbg,multispin,window,serving,serving_full",
                     help="comma-separated legs to run besides the headline: plain, sk, sk_gauss, uneven, "
-                         "rrbg, window, serving, serving_full")
+                         "rrbg, multispin, window, serving, serving_full")
+    ap.add_argument("--multispin-sweeps", type=int, default=256)
     ap.add_argument("--sk-gauss-sweeps", type=int, default=64)
     ap.add_argument("--skip-headline", action="store_true",
                     help="run only the chosen legs (for profiling one leg; no headline value)")
@@ -593,7 +644,7 @@ def main():
     if not args.skip_headline:
         vb = run_vb_batched(args, torch, sg, workloads)
         log("VB batched: %.1f updates/ns" % vb["value"])
-    plain = sk = uneven = rrbg = serve = window = serve_full = sk_gauss = None
+    plain = sk = uneven = rrbg = serve = window = serve_full = sk_gauss = multispin = None
     legs = set() if args.only_vb else set(x.strip() for x in args.legs.split(","))
     if "plain" in legs:
         plain = run_vb_plain(args, torch, sg, workloads)
@@ -610,6 +661,10 @@ def main():
     if "rrbg" in legs:
         rrbg = run_rrbg(args, torch, sg, workloads)
         log("VB RRBG: %.1f updates/ns" % rrbg["updates_per_ns"])
+    if "multispin" in legs:
+        multispin = run_multispin(args, torch, sg, workloads)
+        log("VB multispin: %.1f updates/ns (per-chain layout %.1f)" % (multispin["multispin"]["updates_per_ns"],
+                                                                        multispin["per_chain"]["updates_per_ns"]))
     if "window" in legs:
         window = run_window(args, torch, sg, workloads)
         log("VB windowed C: %.1f updates/ns" % window["updates_per_ns"])
@@ -621,7 +676,8 @@ def main():
         log("serving (configured lengths): p50 %.1f ms, p99 %.1f ms, %.1f updates/ns"
             % (serve_full.get("p50_ms", 0), serve_full.get("p99_ms", 0), serve_full["updates_per_ns"]))
     if vb is None:
-        print(json.dumps({"legs": dict(plain=plain, sk=sk, sk_gauss=sk_gauss, uneven=uneven, rrbg=rrbg, window=window,
+        print(json.dumps({"legs": dict(plain=plain, sk=sk, sk_gauss=sk_gauss, uneven=uneven, rrbg=rrbg,
+                                       multispin=multispin, window=window,
                                        serving=serve, serving_full=serve_full)}), flush=True)
         return
     cpu = None
@@ -659,6 +715,7 @@ def main():
         "sk_gauss": sk_gauss,
         "uneven": uneven,
         "rrbg": rrbg,
+        "multispin": multispin,
         "window": window,
         "serving": serve,
         "serving_configured": serve_full,

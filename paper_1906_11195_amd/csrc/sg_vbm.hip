@@ -361,8 +361,9 @@ hipError_t vbm_prepare()
     static const hipError_t a1 = hipFuncSetAttribute((const void*)vbm_sweep_kernel,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (a1 != hipSuccess) return a1;
+    // the bond kernel also has static LDS: ask for the dynamic part it uses
     static const hipError_t a2 = hipFuncSetAttribute((const void*)vbm_bond_kernel,
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, kVbmMaxN * 8);
     return a2;
 }
 
