@@ -360,8 +360,8 @@ def run_rrbg(args, torch, sg, workloads):
 
 def run_multispin(args, torch, sg, workloads):
     """The paper's multispin workload (Methods; SI bipartite-graph section):
-    96 random regular bipartite graphs (degree 4, N = 16384), 32 coupling
-    samples x 2 replicas on each = 6144 chains, T cycling over {0.6, 0.8,
+    256 random regular bipartite graphs (degree 4, N = 8192), 32 coupling
+    samples x 2 replicas on each = 16384 chains, T cycling over {0.6, 0.8,
     1.2}.  Run in the multispin layout (64 chains of a graph per 64-bit word)
     and in the per-chain layout (each sample's two replicas share one unit),
     same sweeps, both timed."""
@@ -370,8 +370,8 @@ def run_multispin(args, torch, sg, workloads):
     gen_s = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     S = args.multispin_sweeps
-    out = dict(workload="VB multispin: 96 RRBG graphs (degree 4, N=16384) x 32 coupling samples x 2 replicas "
-                        "= 6144 chains, T{0.6,0.8,1.2}; sweeps 16..%d" % (16 + S), generate_s=round(gen_s, 2))
+    out = dict(workload="VB multispin: 256 RRBG graphs (degree 4, N=8192) x 32 coupling samples x 2 replicas "
+                        "= 16384 chains, T{0.6,0.8,1.2}; sweeps 16..%d" % (16 + S), generate_s=round(gen_s, 2))
     n_total = sum(d.n for d in descs) * 2
     res = {}
     for name, ms in (("multispin", True), ("per_chain", False)):
@@ -385,14 +385,16 @@ def run_multispin(args, torch, sg, workloads):
         e0.record(stream)
         sg.sg_sweep(ctx, S, stream)
         e1.record(stream)
-        r = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = sg.sg_measure(ctx, sg.MEASURE_OBS, stream)
+        measure_ms = (time.perf_counter() - t0) * 1e3
         sg.sg_free(ctx)
         dev_s = e0.elapsed_time(e1) * 1e-3
         res[name] = r
         out[name] = dict(updates_per_ns=n_total * S / (el * 1e9), sweep_kernel_updates_per_ns=n_total * S / (dev_s * 1e9),
-                         create_s=round(create_s, 2))
+                         create_s=round(create_s, 2), measure_ms=round(measure_ms, 1))
     # bytes per chain-update by the scope table's model, r chains sharing the
     # graph stream, plus the per-chain couplings the multispin layout reads
     # with it (one bit per chain and adjacency entry: c / 8 B)

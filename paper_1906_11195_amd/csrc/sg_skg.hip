@@ -30,6 +30,7 @@ namespace sg {
 namespace {
 
 constexpr int kSkgThreads = 256;
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct SkgLds {
     double* H;          // [n]
@@ -87,6 +88,7 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
     for (int32_t w = tid; w < wn + 2; w += nthr) L.bits[w] = w < wn ? gl(ch->state)[w] : 0u;
     __syncthreads();
     const int32_t NB = (n + 63) >> 6;
+    const bool vec4 = (n & 3) == 0;   // rows start 16-byte aligned
     unsigned long long acc = 0;   // accepted flips (wave 0, lane 0)
 
     for (int32_t s = 0; s < nsw; ++s) {
@@ -95,9 +97,20 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
             const int32_t p0 = b << 6;
             const int32_t m = min(64, n - p0);
             // 1. the block's coupling tile: T[i][j] = J[p0 + i][p0 + j]
-            for (int32_t idx = tid; idx < 64 * 64; idx += nthr) {
-                const int32_t i = idx >> 6, j = idx & 63;
-                L.tile[idx] = (i < m && j < m) ? J[(int64_t)(p0 + i) * n + p0 + j] : 0.0f;
+            //    (16-byte loads when the rows are 16-byte aligned)
+            if (vec4) {
+#pragma unroll 4
+                for (int32_t idx = tid; idx < 64 * 16; idx += nthr) {
+                    const int32_t i = idx >> 4, j = (idx & 15) << 2;
+                    v4f v = {0.f, 0.f, 0.f, 0.f};
+                    if (i < m && j < m) v = *(const SG_G v4f*)(J + (int64_t)(p0 + i) * n + p0 + j);
+                    *(v4f*)(L.tile + (i << 6) + j) = v;   // m is a multiple of 4 here
+                }
+            } else {
+                for (int32_t idx = tid; idx < 64 * 64; idx += nthr) {
+                    const int32_t i = idx >> 6, j = idx & 63;
+                    L.tile[idx] = (i < m && j < m) ? J[(int64_t)(p0 + i) * n + p0 + j] : 0.0f;
+                }
             }
             __syncthreads();
             // 2. decisions (wavefront 0)
@@ -132,17 +145,65 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
             }
             __syncthreads();
             // 3. the block's flips reach every other field, in flip order
+            //    (fields after a flip's lane in the block already have it);
+            //    each thread takes 4 consecutive fields and loads the rows of
+            //    up to 8 flips at once
             const int32_t nf = L.nflip[0];
-            for (int32_t f = 0; f < nf; ++f) {
-                const int32_t e = L.flips[f];
-                const int32_t i = p0 + (e & 63);
-                const double a = e < 0 ? -2.0 : 2.0;
-                const SG_G float* __restrict__ row = J + (int64_t)i * n;
-                for (int32_t k = tid; k < n; k += nthr) {
-                    // fields after the flip's lane in the block were updated
-                    // when the flip was decided
-                    if (k > i && k < p0 + m) continue;
-                    L.H[k] = L.H[k] + a * (double)row[k];
+            if (nf > 0) {
+                if (vec4) {
+                    for (int32_t k4 = tid; k4 < (n >> 2); k4 += nthr) {
+                        const int32_t k0 = k4 << 2;
+                        double h[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) h[c] = L.H[k0 + c];
+                        for (int32_t f0 = 0; f0 < nf; f0 += 8) {
+                            v4f v[8];
+                            int32_t fi[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int32_t f = f0 + u;
+                                fi[u] = f < nf ? L.flips[f] : 0;
+                                const v4f z = {0.f, 0.f, 0.f, 0.f};
+                                v[u] = z;
+                                if (f < nf) v[u] = *(const SG_G v4f*)(J + (int64_t)(p0 + (fi[u] & 63)) * n + k0);
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                if (f0 + u >= nf) break;
+                                const int32_t i = p0 + (fi[u] & 63);
+                                const double a = fi[u] < 0 ? -2.0 : 2.0;
+                                const float vv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) {
+                                    const int32_t k = k0 + c;
+                                    if (!(k > i && k < p0 + m)) h[c] = h[c] + a * (double)vv[c];
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) L.H[k0 + c] = h[c];
+                    }
+                } else {
+                    for (int32_t k = tid; k < n; k += nthr) {
+                        double h = L.H[k];
+                        for (int32_t f0 = 0; f0 < nf; f0 += 8) {
+                            float v[8];
+                            int32_t fi[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int32_t f = f0 + u;
+                                fi[u] = f < nf ? L.flips[f] : 0;
+                                v[u] = f < nf ? J[(int64_t)(p0 + (fi[u] & 63)) * n + k] : 0.0f;
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                if (f0 + u >= nf) break;
+                                const int32_t i = p0 + (fi[u] & 63);
+                                if (!(k > i && k < p0 + m)) h = h + (fi[u] < 0 ? -2.0 : 2.0) * (double)v[u];
+                            }
+                        }
+                        L.H[k] = h;
+                    }
                 }
             }
             __syncthreads();

@@ -20,8 +20,8 @@ couplings, SI sections on the SK model and on the bipartite graph).
   serving     Poisson arrivals; 70 % VB with N log-uniform in [2^12, 2^20],
               30 % SK with N log-uniform in [512, 8192]; T ~ U[0.5, 0.9];
               2^k sweeps, k uniform in {12..16}; seed 5.
-  VB multispin  96 random regular bipartite graphs (degree 4, N = 16384),
-              each with 32 coupling samples x 2 replicas (6144 chains), seed 8.
+  VB multispin  256 random regular bipartite graphs (degree 4, N = 8192),
+              each with 32 coupling samples x 2 replicas (16384 chains), seed 8.
   VB RRBG     the paper's graph ensemble (SI, bipartite-graph section): 256
               random regular bipartite graphs of degree 4, N = 65536, +-1
               couplings, x T in {0.6, 0.8, 1.2} x 2 replicas, seed 6; the
@@ -195,14 +195,14 @@ def random_regular_edges(n: int, z: int, seed: int, bipartite: bool = False):
     return e.astype(np.int32), J
 
 
-def vb_multispin_batched(n_graphs: int = 96, n: int = 16384, samples: int = 32, z: int = 4,
+def vb_multispin_batched(n_graphs: int = 256, n: int = 8192, samples: int = 32, z: int = 4,
                          temps=(0.6, 0.8, 1.2), seed: int = 8) -> List[VbDesc]:
     """The paper's multispin workload shape (Methods; SI bipartite-graph
     section): random regular bipartite graphs of degree z, each carrying
     `samples` independent +-1 coupling sets (numpy default_rng(seed * 1000003
-    + graph)), 2 replicas per sample, temperatures cycling over `temps`; 96 x
-    32 x 2 = 6144 chains of 16384 spins (about the headline's 1e8
-    chain-updates per sweep)."""
+    + graph)), 2 replicas per sample, temperatures cycling over `temps`; 256 x
+    32 x 2 = 16384 chains of 8192 spins (1.3e8 chain-updates per sweep, near
+    the headline's 1.0e8)."""
     out = []
     for g in range(n_graphs):
         edges, _ = random_regular_edges(n, z, seed * 1000003 + g, bipartite=True)
