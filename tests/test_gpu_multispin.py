@@ -106,3 +106,17 @@ def test_multispin_generated_graph_shares_couplings():
     descs = [sg.VbDesc(n=4096, T=T, seed=2, instance_id=k, graph_id=1) for k, T in
              enumerate([0.6, 0.8, 1.2] * 3)]
     check(descs, [64], 64)
+
+
+def test_multispin_benchmark_shape_sampled():
+    # units of the benchmark's multispin leg (RRBG, N = 8192, 32 coupling
+    # samples x 2 replicas per graph): four graphs, a prefix of 24 sweeps,
+    # sampled instances against the oracle
+    require_gpu()
+    from paper_1906_11195_amd import workloads
+    descs = workloads.vb_multispin_batched(n_graphs=4)
+    res = run_lib(descs, [10, 14], workloads.VB_BATCHED_SWEEPS, multispin=True)
+    picks = [0, 31, 45, 127]
+    refs = oracle_all([descs[i] for i in picks], 24, workloads.VB_BATCHED_SWEEPS)
+    for i, ref in zip(picks, refs):
+        assert_instance_equal(res, i, ref, label="bench-shape inst %d" % i)

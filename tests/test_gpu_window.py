@@ -81,3 +81,27 @@ def test_window_uneven_batch_with_autotune():
     ns = [int(2 ** (10 + 7 * u)) for u in rng.random(12)]
     descs = [sg.VbDesc(n=n, T=[0.6, 0.8, 1.0][k % 3], seed=4, instance_id=k, graph_id=k) for k, n in enumerate(ns)]
     check(descs, [64, 64], 128, 32, autotune=True, graph=True)
+
+
+def test_window_full_batched_context_sampled():
+    # the benchmark's windowed leg: all 768 instances (1536 chains, N = 65536,
+    # 14 waiting times <= 2^12) in one context, a prefix of 40 sweeps,
+    # sampled instances against the oracle
+    require_gpu()
+    from paper_1906_11195_amd import workloads
+    descs = workloads.vb_batched()
+    t_max, tw_max = workloads.VB_BATCHED_SWEEPS, 4096
+    ctx = sg.sg_create_vb(descs, t_max=t_max, window_tw_max=tw_max)
+    try:
+        sg.sg_sweep(ctx, 17)
+        sg.sg_sweep(ctx, 23)
+        res = sg.sg_measure(ctx, sg.MEASURE_OBS)
+    finally:
+        sg.sg_free(ctx)
+    picks = [0, 383, 767]
+    with cf.ThreadPoolExecutor(max_workers=3) as ex:
+        refs = list(ex.map(lambda i: oracle_window(descs[i], 40, t_max, tw_max), picks))
+    assert np.array_equal(res["window_count"], refs[0]["window_count"])
+    for i, ref in zip(picks, refs):
+        assert np.array_equal(res["window"][i], ref["window"]), "window sums, inst %d" % i
+        assert np.array_equal(res["gram"][i], ref["gram"]) and np.array_equal(res["bond"][i], ref["bond"])
