@@ -39,7 +39,13 @@ namespace {
 
 constexpr int kDMax = 8;   // adjacency entries prefetched per position
 constexpr int kTab = 128;  // threshold table per chain: index 64 + x, -63 <= x <= 63
+constexpr int kThc = 32;   // compact threshold table per chain: index 15 - x, -16 <= x <= 15
 constexpr int kMaxCls = 64; // colour classes (greedy colouring, degree <= 63)
+// LDS byte offsets of the flip-spreading table (256 words) and of the spin
+// words: the compact tables come first, so that all three are addressed
+// with the instructions' constant offsets
+constexpr uint32_t kSprOff = kVbMaxChains * kThc * 4;
+constexpr uint32_t kSpOff = kSprOff + 256 * 4;
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -64,7 +70,9 @@ struct Sl {
 };
 
 struct VbLds {
-    uint32_t* sp;                 // spins, VbLayout words
+    uint32_t* thc;                // [8][kThc] at LDS offset 0: 15 - x -> thr[x] >> 16; 0x10000 for x <= 0
+    uint32_t* spr;                // [256] at kSprOff: bit c of v -> bit 4 c of spr[v]
+    uint32_t* sp;                 // spins, VbLayout words, at LDS offset kSpOff
     uint32_t sp_lds;              // the same array as a byte offset in LDS
     uint32_t* thr;                // [8][kTab]: 64 - x -> thr[x] >> 16; 0x10000 for x <= 0
     unsigned long long* accs;     // [8]
@@ -85,9 +93,11 @@ __host__ __device__ __forceinline__ int32_t vb_batch_chunks(int32_t nch)
 __device__ __forceinline__ VbLds vb_carve(uint32_t* smem, uint32_t smem_lds, int32_t sw, int nthr, int32_t nch)
 {
     VbLds L;
-    L.sp = smem;
-    L.sp_lds = smem_lds;
-    L.thr = smem + ((sw + 3) & ~3);
+    L.thc = smem;
+    L.spr = smem + kSprOff / 4;
+    L.sp = smem + kSpOff / 4;
+    L.sp_lds = smem_lds + kSpOff;
+    L.thr = L.sp + ((sw + 3) & ~3);
     L.accs = (unsigned long long*)(L.thr + kVbMaxChains * kTab);
     L.flag = (int32_t*)(L.accs + kVbMaxChains);
     L.cls = L.flag + 4;
@@ -183,82 +193,142 @@ __device__ __forceinline__ void load_ents(PE ent, Stage& st)
 
 // Metropolis decisions of one chunk for every chain, from the unsatisfied-bond
 // counts: chain c's count is the `width`-bit field of cA (c even or RPAD < 8)
-// or cB (c odd, RPAD 8) at bit fsh(c).  Returns this lane's flips in spin-word
-// form (chain c's flip at bit c P); acc[c] += chain c's accepted flips.
+// or cB (c odd, RPAD 8, 8-bit fields) at bit fsh(c).  Returns this lane's
+// flips in spin-word form (chain c's flip at bit c P).  The counts index the
+// full tables (x = deg - 2 cnt at word c kTab + 64 - x).
 template <int RPAD>
-__device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, const VbLds& L, const uint32_t* gx,
-                                              uint32_t cA, uint32_t cB, bool wide, int32_t deg, bool act,
-                                              int32_t q, uint32_t t, int32_t nch, uint64_t key, uint32_t* acc)
+__device__ __forceinline__ uint32_t vb_decide_full(const VbUnit* __restrict__ up, const VbLds& L,
+                                                   const uint32_t* gx, uint32_t cA, uint32_t cB, int32_t deg,
+                                                   bool act, int32_t q, uint32_t t, int32_t nch, uint64_t key)
 {
     using S = Sl<RPAD>;
     const int lane = threadIdx.x & 63;
     const uint32_t hsel = (uint32_t)lane & 7u;
-    // RPAD 8: the 4-bit fields (chain c at bit 4c of cA) are spread to the
-    // 8-bit layout (even chains in cA, odd chains in cB, chain c at byte
-    // c / 2), so every count is extracted at a constant position and width
-    if (RPAD == 8 && !wide) {
-        cB = (cA >> 4) & 0x0F0F0F0Fu;
-        cA &= 0x0F0F0F0Fu;
-    }
     constexpr uint32_t width = RPAD == 8 ? 8u : (uint32_t)S::P;
+    // (the counts are selected as values: a selected reference would put
+    // cA and cB in private memory when c is not a constant)
     auto count = [&](int c) -> uint32_t {
-        if (RPAD == 1) return cA;
+        const uint32_t a = cA, b = cB;
+        if (RPAD == 1) return a;
         const uint32_t fsh = RPAD == 8 ? 8u * (uint32_t)(c >> 1) : (uint32_t)(c * S::P);
-        return __builtin_amdgcn_ubfe(RPAD == 8 && (c & 1) ? cB : cA, fsh, width);
+        return __builtin_amdgcn_ubfe(RPAD == 8 && (c & 1) ? b : a, fsh, width);
     };
-    // The table holds chain c's entry for x at word c kTab + 64 - x, so the
-    // entry for x = deg - 2 cnt is at byte 4 (64 - deg) + 8 cnt; `tb` includes
-    // the lane's 4 (64 - deg), so each address is a single shift-add
+    // `tb` includes the lane's 4 (64 - deg), so each address is a single
+    // shift-add
     const char* tb = (const char*)L.thr + (uint32_t)(64 - deg) * 4u;
+    auto thr_of = [&](int c, uint32_t cnt) -> uint32_t { return *(const uint32_t*)(tb + c * kTab * 4 + (cnt << 3)); };
     const uint32_t hs = 16u * (hsel & 1u);
-    const unsigned long long am = __builtin_amdgcn_ballot_w64(act);
     uint32_t fl = 0;
-    bool tie = false;   // a lane mask: stays in scalar registers
+    bool tie = false;
 #pragma unroll
     for (int c = 0; c < RPAD; ++c) {
         if (c < nch) {
-            const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (count(c) << 3));
+            const uint32_t th = thr_of(c, count(c));
             const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
-            const bool f = rh < th;
-            const unsigned long long m = __builtin_amdgcn_ballot_w64(f) & am;
             tie = tie || rh == th;
-            acc[c] += (uint32_t)__popcll(m);
-            fl |= (f && act) ? 1u << (c * S::P) : 0u;
+            fl |= rh < th ? 1u << (c * S::P) : 0u;
         }
     }
-    if ((__builtin_amdgcn_ballot_w64(tie) & am) != 0ull) {
+    fl = act ? fl : 0u;
+    if (__builtin_amdgcn_ballot_w64(act && tie) != 0ull) {
         // A equals the high half of the threshold (those lanes did not flip
-        // above): decide on the low half
-#pragma unroll
-        for (int c = 0; c < RPAD; ++c) {
-            if (c < nch) {
-                const uint32_t cnt = count(c);
-                const uint32_t th = *(const uint32_t*)(tb + c * kTab * 4 + (cnt << 3));
-                const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
-                const bool ti = act && rh == th;
-                if (__builtin_amdgcn_ballot_w64(ti) != 0ull) {
-                    bool f2 = false;
-                    if (ti) {
-                        const int32_t x = deg - 2 * (int32_t)cnt;
-                        const U4 Bk = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
-                        f2 = half_word(Bk, hsel) < gl(&up->thr_lo[c][0])[x];
-                    }
-                    acc[c] += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(f2));
-                    fl |= f2 ? 1u << (c * S::P) : 0u;
+        // above): decide on the low half (rare: a loop, not unrolled)
+#pragma unroll 1
+        for (int c = 0; c < nch; ++c) {
+            const uint32_t cnt = count(c);
+            const uint32_t th = thr_of(c, cnt);
+            const uint32_t rh = __builtin_amdgcn_ubfe(gx[4 * c], hs, 16u);
+            const bool ti = act && rh == th;
+            if (__builtin_amdgcn_ballot_w64(ti) != 0ull) {
+                bool f2 = false;
+                if (ti) {
+                    const int32_t x = deg - 2 * (int32_t)cnt;
+                    const U4 Bk = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
+                    f2 = half_word(Bk, hsel) < gl(&up->thr_lo[c][0])[x];
                 }
+                fl |= f2 ? 1u << (c * S::P) : 0u;
             }
         }
     }
     return fl;
 }
 
-// Updates the positions of one chunk for every chain of the unit.  acc[c]
-// (wave-uniform) counts chain c's accepted flips since the last flush.
-// gx: this lane's group's Philox blocks of the chunk (chain c at gx + 4 c).
+// The same with 8 chain slots and every degree of the chunk below 16 (the
+// usual case), in fewer instructions.  The 4-bit counts are spread to bytes
+// (even chains in oE, odd chains in oO, chain c at byte c / 2) and each byte
+// is turned, for all chains at once, into the byte offset 4 (15 - x) = 60 -
+// 4 deg + 8 cnt of the chain's entry in its compact table at LDS offset 0,
+// so that one bit-field extract per chain addresses its threshold; the
+// lane's random half-word is read as such, and e = A - thr (|e| < 2^17)
+// decides: a flip iff e < 0, a tie iff e = 0.  The sign bits are shifted into a flip vector (bit c: chain c, from
+// the highest chain down), which the spreading table turns into spin-word
+// form; ties are detected by the running unsigned minimum of e.
+__device__ __forceinline__ uint32_t vb_decide_compact(const VbUnit* __restrict__ up, const VbLds& L,
+                                                      const uint32_t* gx, uint32_t cA, int32_t deg, bool act,
+                                                      int32_t q, uint32_t t, int32_t nch, uint64_t key)
+{
+    typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+    const int lane = threadIdx.x & 63;
+    // (60 - 4 deg) in every byte
+    const uint32_t bias = __builtin_amdgcn_perm(0u, (uint32_t)(60 - 4 * deg), 0u);
+    const uint32_t oE = ((cA & 0x0F0F0F0Fu) << 3) + bias;          // chain 2k at byte k
+    const uint32_t oO = (((cA >> 4) & 0x0F0F0F0Fu) << 3) + bias;   // chain 2k + 1 at byte k
+    const uint16_t* rp = (const uint16_t*)gx + (lane & 1);        // chain c's A at rp[8 c]
+    uint32_t fv = 0u, emin = 0xFFFFFFFFu;
+    auto chain = [&](int c) {
+        const uint32_t off = __builtin_amdgcn_ubfe((c & 1) ? oO : oE, 8u * (uint32_t)(c >> 1), 8u);
+        const uint32_t e = (uint32_t)rp[8 * c] - *(lds_u32*)(size_t)(off + (uint32_t)(c * kThc * 4));
+        fv = __builtin_amdgcn_alignbit(fv, e, 31u);
+        emin = min(emin, e);
+    };
+    // a unit with 8 slots has 5 to 8 chains: chains 0..4 are decided without
+    // a test (in one block, so that their LDS reads are issued together)
+#pragma unroll
+    for (int c = kVbMaxChains - 1; c >= 5; --c)
+        if (c < nch) chain(c);
+#pragma unroll
+    for (int c = 4; c >= 0; --c) chain(c);
+    fv = act ? fv : 0u;
+    uint32_t fl = *(lds_u32*)(size_t)(kSprOff + fv * 4u);
+    if (__builtin_amdgcn_ballot_w64(act && emin == 0u) != 0ull) {
+        // A equals the high half of the threshold (those lanes did not flip
+        // above): decide on the low half (rare: a loop, not unrolled)
+        const uint32_t hsel = (uint32_t)lane & 7u;
+#pragma unroll 1
+        for (int c = 0; c < nch; ++c) {
+            const uint32_t src = (c & 1) ? oO : oE;
+            const uint32_t off = __builtin_amdgcn_ubfe(src, 8u * (uint32_t)(c >> 1), 8u);
+            const bool ti = act && (uint32_t)rp[8 * c] == *(lds_u32*)(size_t)(off + (uint32_t)(c * kThc * 4));
+            if (__builtin_amdgcn_ballot_w64(ti) != 0ull) {
+                bool f2 = false;
+                if (ti) {
+                    const int32_t x = 15 - (int32_t)(off >> 2);
+                    const U4 Bk = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, up->rep[c], up->inst[c]);
+                    f2 = half_word(Bk, hsel) < gl(&up->thr_lo[c][0])[x];
+                }
+                fl |= f2 ? 1u << (4 * c) : 0u;
+            }
+        }
+    }
+    return fl;
+}
+
+template <int RPAD>
+__device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, const VbLds& L, const uint32_t* gx,
+                                              uint32_t cA, uint32_t cB, bool wide, int32_t deg, bool act,
+                                              int32_t q, uint32_t t, int32_t nch, uint64_t key)
+{
+    if (RPAD == 8 && !wide) return vb_decide_compact(up, L, gx, cA, deg, act, q, t, nch, key);
+    return vb_decide_full<RPAD>(up, L, gx, cA, cB, deg, act, q, t, nch, key);
+}
+
+// Updates the positions of one chunk for every chain of the unit and returns
+// this lane's flips in spin-word form.  gx: this lane's group's Philox blocks
+// of the chunk (chain c at gx + 4 c).
 template <int RPAD, bool SPLIT, class PE>
-__device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const VbLds& L, PE ent, const Stage& st,
-                                         int32_t lo, int32_t hi, uint32_t t, int32_t nch,
-                                         uint64_t key, const uint32_t* gx, uint32_t* acc)
+__device__ __forceinline__ uint32_t vb_chunk(const VbUnit* __restrict__ up, const VbLds& L, PE ent, const Stage& st,
+                                             int32_t lo, int32_t hi, uint32_t t, int32_t nch,
+                                             uint64_t key, const uint32_t* gx)
 {
     using S = Sl<RPAD>;
     // adjacency resident in LDS: such units are small and bound by the
@@ -271,8 +341,8 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
     const bool act = q >= lo && q < hi;
     const int32_t deg = st.r1 - st.r0;   // 0 on inactive lanes
     // spin words read through a local-address-space pointer made from the
-    // array's LDS offset (the constant 0), so that the base is neither kept
-    // in a register nor re-read for every neighbour
+    // array's LDS offset (the constant kSpOff), so that the base is neither
+    // kept in a register nor re-read for every neighbour
     const uint32_t spo = L.sp_lds;
     auto spw = [&](uint32_t off) -> uint32_t {
         return *(const __attribute__((address_space(3))) uint32_t*)(size_t)(spo + off);
@@ -322,7 +392,7 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
         }
     }
 
-    const uint32_t fl = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key, acc);
+    const uint32_t fl = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key);
     // write the flips back: every lane XORs its flips into its spin word (the
     // P lanes of a word are in this wavefront's chunk, nothing else writes it)
     if (fl)
@@ -336,6 +406,7 @@ __device__ __forceinline__ void vb_chunk(const VbUnit* __restrict__ up, const Vb
             if (wi < (uint32_t)up->state_words) gl(up->state)[wi] = spw(wi * 4u);
         }
     }
+    return fl;
 }
 
 // Split units: after a colour class, the members publish the words they
@@ -633,6 +704,17 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
         const int c = i / kTab, x = 64 - (i - c * kTab);
         L.thr[i] = x <= 0 ? 0x10000u : x < kVbXMax ? gl(&up->thr_hi[c][0])[x] : 0u;
     }
+    // the same for |x| <= 15 in the compact tables: word c kThc + j holds the
+    // entry for x = 15 - j
+    for (int i = tid; i < kVbMaxChains * kThc; i += nthr) {
+        const int c = i / kThc, x = 15 - (i - c * kThc);
+        L.thc[i] = x <= 0 ? 0x10000u : gl(&up->thr_hi[c][0])[x];
+    }
+    for (int i = tid; i < 256; i += nthr) {
+        uint32_t v = 0;
+        for (int c = 0; c < 8; ++c) v |= (uint32_t)((i >> c) & 1) << (4 * c);
+        L.spr[i] = v;
+    }
     if (tid < kVbMaxChains) {
         L.accs[tid] = 0;
         L.ri[2 * tid] = up->rep[tid];
@@ -661,6 +743,94 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
     if (tid < nch) atomicAdd(up->accepted[tid], L.accs[tid]);
 }
 
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+    return v;
+}
+
+// Accepted flips of one wavefront, counted per lane in the flips' own
+// spin-word fields (n += flips of each chunk).  A P-bit field holds the flips
+// of at most 2^P - 1 chunks: with 8 chain slots (4-bit fields) the counts move
+// to byte fields (e: even chains, o: odd chains, chain c at byte c / 2) every
+// 15 chunks; byte and 16-bit fields are summed over the wavefront into the
+// unit's LDS totals every 255 (65535) chunks, and every field at the end of
+// each sweep.
+template <int RPAD>
+struct VbAcc {
+    uint32_t n = 0, e = 0, o = 0;   // per lane
+    int32_t cn = 0, cb = 0;         // wave-uniform chunk counts since the last fold / flush
+};
+
+template <int RPAD>
+__device__ __forceinline__ void acc_fold(VbAcc<RPAD>& a)
+{
+    if (RPAD == 8) {
+        a.e += a.n & 0x0F0F0F0Fu;
+        a.o += (a.n >> 4) & 0x0F0F0F0Fu;
+        a.n = 0u;
+    }
+    a.cn = 0;
+}
+
+template <int RPAD>
+__device__ __forceinline__ void acc_flush(VbAcc<RPAD>& a, const VbLds& L, int32_t nch)
+{
+    const int lane = threadIdx.x & 63;
+    // chain sums in 16-bit halves (at most 64 x 255 each) or whole words
+    auto put = [&](int c, uint32_t v) {
+        if (lane == 0 && c < nch && v != 0u) atomicAdd(&L.accs[c], (unsigned long long)v);
+    };
+    if (RPAD == 8) {
+        const uint32_t e0 = wave_sum(a.e & 0x00FF00FFu), e1 = wave_sum((a.e >> 8) & 0x00FF00FFu);
+        const uint32_t o0 = wave_sum(a.o & 0x00FF00FFu), o1 = wave_sum((a.o >> 8) & 0x00FF00FFu);
+        put(0, e0 & 0xFFFFu);
+        put(4, e0 >> 16);
+        put(2, e1 & 0xFFFFu);
+        put(6, e1 >> 16);
+        put(1, o0 & 0xFFFFu);
+        put(5, o0 >> 16);
+        put(3, o1 & 0xFFFFu);
+        put(7, o1 >> 16);
+        a.e = 0u;
+        a.o = 0u;
+    } else if (RPAD == 4) {
+        const uint32_t s0 = wave_sum(a.n & 0x00FF00FFu), s1 = wave_sum((a.n >> 8) & 0x00FF00FFu);
+        put(0, s0 & 0xFFFFu);
+        put(2, s0 >> 16);
+        put(1, s1 & 0xFFFFu);
+        put(3, s1 >> 16);
+        a.n = 0u;
+    } else if (RPAD == 2) {
+        put(0, wave_sum(a.n & 0xFFFFu));
+        put(1, wave_sum(a.n >> 16));
+        a.n = 0u;
+    } else {
+        put(0, wave_sum(a.n));
+        a.n = 0u;
+    }
+    a.cn = 0;
+    a.cb = 0;
+}
+
+template <int RPAD>
+__device__ __forceinline__ void acc_add(VbAcc<RPAD>& a, uint32_t fl, const VbLds& L, int32_t nch)
+{
+    a.n += fl;
+    ++a.cn;
+    if (RPAD == 8) {
+        if (a.cn == 15) {
+            acc_fold(a);
+            if (++a.cb == 17) acc_flush(a, L, nch);
+        }
+    } else if (RPAD == 4) {
+        if (a.cn == 255) acc_flush(a, L, nch);
+    } else if (RPAD == 2) {
+        if (a.cn == 65535) acc_flush(a, L, nch);
+    }
+}
+
 // The sweep loop of one unit (or of one member of a split unit: `wave` and
 // `W` then count the wavefronts of all members), for adjacency pointers in
 // HBM or in LDS.  False if a split unit's barrier aborted.
@@ -669,7 +839,15 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
                         int32_t nsw, int64_t t_max, int lane, int wave, int W)
 {
     const int tid = threadIdx.x;
-    const int32_t nch = up->nch, ncls = up->ncls;
+    // The unit's scalars arrive through a pointer argument, which the
+    // compiler cannot take as uniform: made explicitly wave-uniform, the
+    // per-chain tests and the sweep loop branch on scalar registers instead
+    // of masking lanes
+    const int32_t nch = __builtin_amdgcn_readfirstlane(up->nch), ncls = __builtin_amdgcn_readfirstlane(up->ncls);
+    nsw = __builtin_amdgcn_readfirstlane(nsw);
+    W = __builtin_amdgcn_readfirstlane(W);
+    t0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)((uint64_t)t0 >> 32)) << 32) |
+                   (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)t0));
     // the Philox key is the same for every lane: kept in scalar registers,
     // so that the per-round keys cost no vector registers
     const uint64_t key = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(up->key >> 32)) << 32) |
@@ -686,58 +864,70 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
     const uint32_t* xg = (const uint32_t*)(L.xch + wl * 64);
     const uint32_t lane_off = (uint32_t)(lane >> 3) * (uint32_t)nch * 4u + (((uint32_t)lane & 7u) >> 1);
 
-    // pipeline: E = chunk to update next (rows + entries), R = the one after
-    // (rows only)
-    Stage E, R;
+    // pipeline: the chunk being updated and the next one (rows + entries)
+    // take turns in E0 and E1, so that no stage is copied; R holds the rows
+    // of the chunk after next
+    Stage E0, E1, R;
+    E1.q = 0;
+    E1.r0 = 0;
+    E1.r1 = 0;
     R.q = 0;
     R.r0 = 0;
     R.r1 = 0;
     Cursor cR = cursor_start(W, wave, cls);
     bool haveR = nsw > 0 && cursor_next(cR, W, wave, ncls, cls, nsw);
     if (haveR) {
-        load_rows(row, cls, cR, lane, E);
-        load_ents(ent, E);
+        load_rows(row, cls, cR, lane, E0);
+        load_ents(ent, E0);
         haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
         if (haveR) load_rows(row, cls, cR, lane, R);
     }
     __syncthreads();
+    if (nsw <= 0) return true;
 
     const FillLane fr = fill_lane(L, lane, nch);
-    uint32_t acc[RPAD];   // wave-uniform; flushed to LDS once per sweep
-#pragma unroll
-    for (int c = 0; c < RPAD; ++c) acc[c] = 0;
+    VbAcc<RPAD> acc;
+
+    // one chunk (j of colour class [lo, hi) in sweep t): C holds it, N
+    // receives the next one.  The stage moves on unconditionally (past the
+    // last chunk of the launch it re-reads valid entries that are not used),
+    // so that the loads issue without branches
+    auto step = [&](const Stage& C, Stage& N, int32_t lo, int32_t hi, int32_t j, uint32_t t)
+                    __attribute__((always_inline)) {
+        N.q = R.q;
+        N.r0 = R.r0;
+        N.r1 = R.r1;
+        load_ents(ent, N);
+        if (haveR) {
+            haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
+            if (haveR) load_rows(row, cls, cR, lane, R);
+        }
+        if (RPAD == 8) {
+            vb_fill_one(L, fr, (uint32_t)(((lo >> 6) + j) << 6), t, wl, lane, key);
+            left = 1;
+            bi = 0;
+        } else if (left == 0) {
+            vb_fill<(RPAD < 8 ? 8 / RPAD : 1)>(L, pc, pc_ok, cls, ncls, nsw, W, wave, wl, lane, t0, nch, key);
+            left = B;
+            bi = 0;
+        }
+        const uint32_t fl = vb_chunk<RPAD, SPLIT>(up, L, ent, C, lo, hi, t, nch, key,
+                                                  xg + (uint32_t)bi * 32u * (uint32_t)nch + lane_off);
+        acc_add(acc, fl, L, nch);
+        --left;
+        ++bi;
+    };
 
     for (int32_t s = 0; s < nsw; ++s) {
         const uint32_t t = (uint32_t)(t0 + s);
         for (int32_t k = 0; k < ncls; ++k) {
             const int32_t lo = cls_at(cls, k), hi = cls_at(cls, k + 1);
             const int32_t nck = n_chunks(cls, k);
+            // chunks in pairs: E0 and E1 take turns; after an odd count the
+            // next chunk is moved back to E0 (once per class)
             for (int32_t j = wave; j < nck; j += W) {
-                // the stage moves on unconditionally (past the last chunk of
-                // the launch it re-reads valid entries that are not used), so
-                // that the registers rotate without branches
-                const Stage cur = E;
-                E.q = R.q;
-                E.r0 = R.r0;
-                E.r1 = R.r1;
-                load_ents(ent, E);
-                if (haveR) {
-                    haveR = cursor_next(cR, W, wave, ncls, cls, nsw);
-                    if (haveR) load_rows(row, cls, cR, lane, R);
-                }
-                if (RPAD == 8) {
-                    vb_fill_one(L, fr, (uint32_t)(((lo >> 6) + j) << 6), t, wl, lane, key);
-                    left = 1;
-                    bi = 0;
-                } else if (left == 0) {
-                    vb_fill<(RPAD < 8 ? 8 / RPAD : 1)>(L, pc, pc_ok, cls, ncls, nsw, W, wave, wl, lane, t0, nch, key);
-                    left = B;
-                    bi = 0;
-                }
-                vb_chunk<RPAD, SPLIT>(up, L, ent, cur, lo, hi, t, nch, key,
-                                      xg + (uint32_t)bi * 32u * (uint32_t)nch + lane_off, acc);
-                --left;
-                ++bi;
+                step(E0, E1, lo, hi, j, t);
+                E0 = E1;
             }
             if (SPLIT) {
                 if (!vb_exchange<RPAD>(up, L, lo, hi, (uint32_t)up->members * (uint32_t)(s * ncls + k + 1)))
@@ -746,13 +936,8 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
                 __syncthreads();
             }
         }
-        if (lane == 0) {
-#pragma unroll
-            for (int c = 0; c < RPAD; ++c)
-                if (c < nch && acc[c]) atomicAdd(&L.accs[c], (unsigned long long)acc[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < RPAD; ++c) acc[c] = 0;
+        acc_fold(acc);
+        acc_flush(acc, L, nch);
         const int64_t tn = t0 + s + 1;
         const bool grid = tn <= t_max && (tn & (tn - 1)) == 0;
         const int32_t kn = grid ? 1 + (63 - __clzll((unsigned long long)tn)) : -1;
@@ -867,7 +1052,7 @@ size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads)
 {
     const size_t sw = (size_t)VbLayout(rpad).words(n);
     const size_t waves = (size_t)threads / 64;
-    return ((sw + 3) & ~(size_t)3) * 4 + (size_t)kVbMaxChains * kTab * 4 + kVbMaxChains * 8 + 16 +
+    return kSpOff + ((sw + 3) & ~(size_t)3) * 4 + (size_t)kVbMaxChains * kTab * 4 + kVbMaxChains * 8 + 16 +
            (kMaxCls + 4) * 4 + kVbMaxChains * 8 + (size_t)kMaxGrid * kVbMaxChains * 4 + waves * 64 * 16;
 }
 
