@@ -227,6 +227,12 @@ typedef struct sg_opts {
  * in LDS); other instances get the per-chain layout.  No effect on any
  * result.  Not combined with SG_OPT_WINDOW (SG_ENOTSUP). */
 #define SG_OPT_MULTISPIN 8u
+/* SG_OPT_PLAIN_LDS: keep no complemented copy of the spin words in LDS.  By
+ * default a per-chain unit that is neither LDS-resident nor split keeps one
+ * when it fits, and its adjacency entries then address the neighbour's word
+ * or its complement by the sign of the coupling.  A layout choice: no effect
+ * on any result. */
+#define SG_OPT_PLAIN_LDS 16u
 
 #define SG_MEASURE_OBS 1u    /* times, bond, overlap, gram, accepted */
 #define SG_MEASURE_SPINS 2u  /* current spins, vertex order */

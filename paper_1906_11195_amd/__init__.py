@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libsgmi.so")
 SG_OK, SG_EINVAL, SG_ENOMEM, SG_EDEVICE, SG_ESTATE, SG_EPARITY, SG_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 START_RANDOM, START_ALIGNED, START_GIVEN = 0, 1, 2
 MEASURE_OBS, MEASURE_SPINS = 1, 2
-OPT_AUTOTUNE, OPT_GRAPH, OPT_WINDOW, OPT_MULTISPIN = 1, 2, 4, 8
+OPT_AUTOTUNE, OPT_GRAPH, OPT_WINDOW, OPT_MULTISPIN, OPT_PLAIN_LDS = 1, 2, 4, 8, 16
 
 EXPORTS = ("sg_create_vb", "sg_create_sk", "sg_sweep", "sg_measure", "sg_measure_noalloc", "sg_free",
            "sg_strerror", "sg_vb_inspect", "sg_sk_inspect", "sg_sk_corrupt_field")
@@ -285,14 +285,17 @@ def _grid_len(t_max):
 def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
                  threads_per_unit: int = 0, torch_alloc: bool = True, autotune: bool = False,
                  graph: bool = False, split_members: int = 0,
-                 window_tw_max: Optional[int] = None, multispin: bool = False) -> Context:
+                 window_tw_max: Optional[int] = None, multispin: bool = False,
+                 plain_lds: bool = False) -> Context:
     """window_tw_max: measure the windowed correlation with the grid times
     <= window_tw_max as waiting times (SG_OPT_WINDOW); multispin: pack the
-    chains of a shared graph 64 per word (SG_OPT_MULTISPIN)."""
+    chains of a shared graph 64 per word (SG_OPT_MULTISPIN); plain_lds: keep
+    no complemented copy of the spin words (SG_OPT_PLAIN_LDS)."""
     keep = []
     arr = (_VbDesc * len(descs))(*[_vb_struct(d, keep) for d in descs])
     flags = (OPT_AUTOTUNE if autotune else 0) | (OPT_GRAPH if graph else 0)
     flags |= OPT_MULTISPIN if multispin else 0
+    flags |= OPT_PLAIN_LDS if plain_lds else 0
     kw = n_bins = 0
     if window_tw_max is not None:
         flags |= OPT_WINDOW

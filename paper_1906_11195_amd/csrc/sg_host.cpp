@@ -650,7 +650,8 @@ void vb_autotune(sg_ctx* c)
             size_t l = 0;
             for (int32_t u = G.first; u < G.first + G.count; ++u) {
                 const VbUnit& U = c->units[(size_t)u];
-                l = std::max(l, vb_lds_bytes(U.n, U.rpad, U.nch, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
+                l = std::max(l, vb_lds_bytes(U.n, U.rpad, U.nch, th, U.cpl != 0) +
+                                    (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
             }
             return l;
         };
@@ -805,6 +806,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         int32_t rpad;
         int threads = 64;
         bool resident = false;
+        bool cpl = false;
         int64_t work = 0;
         int members = 1;
     };
@@ -937,6 +939,15 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         if (sa != sb) return sa;
         return a.threads != b.threads ? a.threads > b.threads : a.work > b.work;
     });
+    // A unit neither resident nor split keeps a complemented copy of its
+    // spin words in LDS when it fits: its adjacency entries then address the
+    // neighbour's word, or its complement for J < 0, directly
+    const bool plain_lds = o && (o->flags & SG_OPT_PLAIN_LDS);
+    for (auto& u : plan) {
+        const VbGraph& g = graphs[(size_t)u.group];
+        u.cpl = !plain_lds && !u.resident && u.members == 1 &&
+                vb_lds_bytes((int32_t)g.n, u.rpad, (int32_t)u.chains.size(), u.threads, true) <= lds_cap;
+    }
     int n_split = 0, n_entries = 0;
     for (const auto& u : plan) {
         n_split += u.members > 1 ? 1 : 0;
@@ -951,6 +962,11 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         off_ent[gi] = A.take((graphs[gi].ent.size() + kVbEntPad) * 4);
         off_cls[gi] = A.take(graphs[gi].cls.size() * 4);
     }
+    // entries in the complemented-copy form: one array per graph and slot count
+    std::map<std::pair<int32_t, int32_t>, size_t> off_entc;
+    for (const auto& u : plan)
+        if (u.cpl && !off_entc.count({u.group, u.rpad}))
+            off_entc[{u.group, u.rpad}] = A.take((graphs[(size_t)u.group].ent.size() + kVbEntPad) * 4);
     std::vector<size_t> off_state(plan.size());
     for (size_t u = 0; u < plan.size(); ++u) {
         const int64_t n = graphs[(size_t)plan[u].group].n;
@@ -1026,6 +1042,12 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         hip_check(hipMemcpy(c->at<void>(off_ent[gi]), padded.data(), padded.size() * 4, hipMemcpyHostToDevice));
         hip_check(hipMemcpy(c->at<void>(off_cls[gi]), g.cls.data(), g.cls.size() * 4, hipMemcpyHostToDevice));
     }
+    for (const auto& kv : off_entc) {
+        const VbGraph& g = graphs[(size_t)kv.first.first];
+        std::vector<uint32_t> e(g.ent.size() + kVbEntPad);
+        vb_cpl_entries(g.ent.data(), g.ent.size(), kVbEntPad, kv.first.second, (int32_t)g.n, e.data());
+        hip_check(hipMemcpy(c->at<void>(kv.second), e.data(), e.size() * 4, hipMemcpyHostToDevice));
+    }
     for (int32_t i = 0; i < count; ++i) {
         if (d[i].start != SG_START_GIVEN) continue;
         const VbGraph& g = graphs[(size_t)c->group_of_inst[(size_t)i]];
@@ -1053,6 +1075,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         U.ent = c->at<uint32_t>(off_ent[(size_t)plan[u].group]);
         U.cls = c->at<int32_t>(off_cls[(size_t)plan[u].group]);
         U.resident = plan[u].resident ? 1 : 0;
+        U.cpl = plan[u].cpl ? 1 : 0;
+        if (U.cpl) U.entc = c->at<uint32_t>(off_entc.at({plan[u].group, plan[u].rpad}));
         U.m2 = (int32_t)g.ent.size();
         // chains of a unit share one graph, hence one seed (graphs are keyed by
         // seed; an explicit edge list belongs to one instance)
@@ -1109,7 +1133,8 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
             G.count++;
         }
         G.updates += g.n * U.nch;
-        G.lds = std::max(G.lds, vb_lds_bytes(U.n, U.rpad, U.nch, th) + (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
+        G.lds = std::max(G.lds, vb_lds_bytes(U.n, U.rpad, U.nch, th, U.cpl != 0) +
+                                    (U.resident ? vb_resident_bytes(U.n, U.m2) : 0));
         c->vb_threads = std::max(c->vb_threads, th);
         c->bond_lds = std::max(c->bond_lds, (size_t)(((U.nch * U.words_n + 1) & ~1) * 4 + kVbMaxChains * 8));
         c->updates_per_sweep += g.n * U.nch;

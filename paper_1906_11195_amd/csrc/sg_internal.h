@@ -97,7 +97,12 @@ hipError_t vb_sweep(const VbUnit* units, int n_units, int threads, size_t lds_by
 hipError_t vb_advance(int64_t* t, int32_t n_sweeps, uint32_t* bars, int n_bar, hipStream_t s);
 // LDS a unit needs for a launch with `threads` lanes per workgroup, and the
 // extra LDS that keeps its whole adjacency resident.
-size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads);
+size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads, bool cpl = false);
+// Adjacency entries (position | (J < 0) << 31) in the form a unit with a
+// complemented copy of its spin words reads: the LDS byte address of the
+// neighbour's word, of its complement when J < 0, above 5 bits of in-word
+// shift; `pad` entries of position 0 follow the m entries.
+void vb_cpl_entries(const uint32_t* ent, size_t m, size_t pad, int32_t rpad, int32_t n, uint32_t* out);
 size_t vb_resident_bytes(int32_t n, int32_t m2);
 
 // Multispin units (sg_vbm.hip).

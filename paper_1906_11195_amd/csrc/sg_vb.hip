@@ -74,6 +74,8 @@ struct VbLds {
     uint32_t* spr;                // [256] at kSprOff: bit c of v -> bit 4 c of spr[v]
     uint32_t* sp;                 // spins, VbLayout words, at LDS offset kSpOff
     uint32_t sp_lds;              // the same array as a byte offset in LDS
+    uint32_t* cp;                 // (units with cpl) the complemented words
+    uint32_t cp_lds;
     uint32_t* thr;                // [8][kTab]: 64 - x -> thr[x] >> 16; 0x10000 for x <= 0
     unsigned long long* accs;     // [8]
     int32_t* flag;                // [4]: split units' abort flag
@@ -90,14 +92,18 @@ __host__ __device__ __forceinline__ int32_t vb_batch_chunks(int32_t nch)
     return nch <= 8 ? (8 / nch > 0 ? 8 / nch : 1) : 1;
 }
 
-__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, uint32_t smem_lds, int32_t sw, int nthr, int32_t nch)
+__device__ __forceinline__ VbLds vb_carve(uint32_t* smem, uint32_t smem_lds, int32_t sw, int nthr, int32_t nch,
+                                          bool cpl)
 {
     VbLds L;
+    const int32_t swp = (sw + 3) & ~3;
     L.thc = smem;
     L.spr = smem + kSprOff / 4;
     L.sp = smem + kSpOff / 4;
     L.sp_lds = smem_lds + kSpOff;
-    L.thr = L.sp + ((sw + 3) & ~3);
+    L.cp = L.sp + swp;
+    L.cp_lds = L.sp_lds + 4u * (uint32_t)swp;
+    L.thr = L.sp + (cpl ? 2 * swp : swp);
     L.accs = (unsigned long long*)(L.thr + kVbMaxChains * kTab);
     L.flag = (int32_t*)(L.accs + kVbMaxChains);
     L.cls = L.flag + 4;
@@ -325,7 +331,7 @@ __device__ __forceinline__ uint32_t vb_decide(const VbUnit* __restrict__ up, con
 // Updates the positions of one chunk for every chain of the unit and returns
 // this lane's flips in spin-word form.  gx: this lane's group's Philox blocks
 // of the chunk (chain c at gx + 4 c).
-template <int RPAD, bool SPLIT, class PE>
+template <int RPAD, bool SPLIT, bool CPL, class PE>
 __device__ __forceinline__ uint32_t vb_chunk(const VbUnit* __restrict__ up, const VbLds& L, PE ent, const Stage& st,
                                              int32_t lo, int32_t hi, uint32_t t, int32_t nch,
                                              uint64_t key, const uint32_t* gx)
@@ -350,8 +356,12 @@ __device__ __forceinline__ uint32_t vb_chunk(const VbUnit* __restrict__ up, cons
     const uint32_t qsh = (uint32_t)q & (uint32_t)(S::P - 1);
     // own word, position q at the field bottoms
     const uint32_t o0 = act ? spw(S::boff((uint32_t)q)) >> qsh : 0u;
-    // bit c P of f: the bond to the neighbour is unsatisfied in chain c
+    // bit c P of f: the bond to the neighbour is unsatisfied in chain c.
+    // With a complemented copy of the words the entry holds the LDS byte
+    // address of the neighbour's word (of its complement when J < 0) above
+    // the in-word shift, which the shift takes from its low 5 bits
     auto unsat = [&](uint32_t en) {
+        if (CPL) return (*(const __attribute__((address_space(3))) uint32_t*)(size_t)(en >> 5) >> (en & 31u)) ^ o0;
         const uint32_t sh = en & (uint32_t)(S::P - 1);
         return (spw(S::boff(en)) >> sh) ^ o0 ^ (uint32_t)((int32_t)en >> 31);
     };
@@ -395,9 +405,14 @@ __device__ __forceinline__ uint32_t vb_chunk(const VbUnit* __restrict__ up, cons
     const uint32_t fl = vb_decide<RPAD>(up, L, gx, cA, cB, wide, deg, act, q, t, nch, key);
     // write the flips back: every lane XORs its flips into its spin word (the
     // P lanes of a word are in this wavefront's chunk, nothing else writes it)
-    if (fl)
-        __atomic_fetch_xor((__attribute__((address_space(3))) uint32_t*)(size_t)(spo + ((uint32_t)q >> S::LP) * 4u),
-                           fl << qsh, __ATOMIC_RELAXED);
+    if (fl) {
+        const uint32_t wo = ((uint32_t)q >> S::LP) * 4u;
+        __atomic_fetch_xor((__attribute__((address_space(3))) uint32_t*)(size_t)(spo + wo), fl << qsh,
+                           __ATOMIC_RELAXED);
+        if (CPL)
+            __atomic_fetch_xor((__attribute__((address_space(3))) uint32_t*)(size_t)(L.cp_lds + wo), fl << qsh,
+                               __ATOMIC_RELAXED);
+    }
     if (SPLIT) {
         // a member of a split unit also writes the chunk's words through to HBM
         wave_sync();
@@ -668,13 +683,13 @@ __device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ u
     }
 }
 
-template <int RPAD, bool SPLIT, class PR, class PE, class PC>
+template <int RPAD, bool SPLIT, bool CPL, class PR, class PE, class PC>
 __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
                         int32_t nsw, int64_t t_max, int lane, int wave, int W);
 
 // (each variant is a function of its own so that its registers are
 // allocated for it alone)
-template <int RPAD, bool RES, bool SPLIT>
+template <int RPAD, bool RES, bool SPLIT, bool CPL>
 __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, uint32_t* smem_arr, uint32_t lds0,
                                                 int64_t t0, int32_t nsw, int64_t t_max)
 {
@@ -693,10 +708,14 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
     const int wave = __builtin_amdgcn_readfirstlane((tid >> 6) + (SPLIT ? up->member * Wl : 0));
     const int W = SPLIT ? up->members * Wl : Wl;
     const int32_t sw = up->state_words, nch = up->nch, ncls = up->ncls;
-    const VbLds L = vb_carve(smem, 0u, sw, nthr, nch);
+    const VbLds L = vb_carve(smem, 0u, sw, nthr, nch, CPL);
 
     const SG_G uint32_t* gstate = gl(up->state);
-    for (int32_t w = tid; w < sw; w += nthr) L.sp[w] = gstate[w];
+    for (int32_t w = tid; w < sw; w += nthr) {
+        const uint32_t v = gstate[w];
+        L.sp[w] = v;
+        if (CPL) L.cp[w] = ~v;
+    }
     if (tid < ((sw + 3) & ~3) - sw) L.sp[sw + tid] = 0u;   // pad to 16 bytes (read by vb_window)
     // chain c's threshold high halves: word c kTab + j holds the entry for
     // x = 64 - j (0x10000 for x <= 0: always accepted)
@@ -731,10 +750,11 @@ __device__ __attribute__((noinline)) void vb_run(const VbUnit* __restrict__ up, 
         uint32_t* re = (uint32_t*)(L.area + n + 1);
         for (int32_t i = tid; i < up->m2 + kVbEntPad; i += nthr) re[i] = i < up->m2 ? gent[i] : 0u;
         __syncthreads();
-        vb_loop<RPAD, false>(up, L, (const int32_t*)L.area, (const uint32_t*)(L.area + n + 1), cls, t0, nsw,
-                             t_max, lane, wave, W);
+        vb_loop<RPAD, false, CPL>(up, L, (const int32_t*)L.area, (const uint32_t*)(L.area + n + 1), cls, t0, nsw,
+                                  t_max, lane, wave, W);
     } else {
-        vb_loop<RPAD, SPLIT>(up, L, gl(up->row), gl(up->ent), cls, t0, nsw, t_max, lane, wave, W);
+        vb_loop<RPAD, SPLIT, CPL>(up, L, gl(up->row), gl(CPL ? up->entc : up->ent), cls, t0, nsw, t_max, lane,
+                                  wave, W);
     }
     // (split units keep `state` current by writing through)
     if (!SPLIT)
@@ -834,7 +854,7 @@ __device__ __forceinline__ void acc_add(VbAcc<RPAD>& a, uint32_t fl, const VbLds
 // The sweep loop of one unit (or of one member of a split unit: `wave` and
 // `W` then count the wavefronts of all members), for adjacency pointers in
 // HBM or in LDS.  False if a split unit's barrier aborted.
-template <int RPAD, bool SPLIT, class PR, class PE, class PC>
+template <int RPAD, bool SPLIT, bool CPL, class PR, class PE, class PC>
 __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, PE ent, PC cls, int64_t t0,
                         int32_t nsw, int64_t t_max, int lane, int wave, int W)
 {
@@ -911,7 +931,7 @@ __device__ bool vb_loop(const VbUnit* __restrict__ up, const VbLds& L, PR row, P
             left = B;
             bi = 0;
         }
-        const uint32_t fl = vb_chunk<RPAD, SPLIT>(up, L, ent, C, lo, hi, t, nch, key,
+        const uint32_t fl = vb_chunk<RPAD, SPLIT, CPL>(up, L, ent, C, lo, hi, t, nch, key,
                                                   xg + (uint32_t)bi * 32u * (uint32_t)nch + lane_off);
         acc_add(acc, fl, L, nch);
         --left;
@@ -975,24 +995,31 @@ __global__ void __launch_bounds__(1024) vb_sweep_kernel(const VbUnit* __restrict
     const int64_t t0 = *gl(t0p);
     if (up->resident) {
         switch (up->rpad) {
-            case 1: vb_run<1, true, false>(up, smem, lds0, t0, nsw, t_max); break;
-            case 2: vb_run<2, true, false>(up, smem, lds0, t0, nsw, t_max); break;
-            case 4: vb_run<4, true, false>(up, smem, lds0, t0, nsw, t_max); break;
-            default: vb_run<8, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 1: vb_run<1, true, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 2: vb_run<2, true, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 4: vb_run<4, true, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            default: vb_run<8, true, false, false>(up, smem, lds0, t0, nsw, t_max); break;
         }
     } else if (up->members > 1) {
         switch (up->rpad) {
-            case 1: vb_run<1, false, true>(up, smem, lds0, t0, nsw, t_max); break;
-            case 2: vb_run<2, false, true>(up, smem, lds0, t0, nsw, t_max); break;
-            case 4: vb_run<4, false, true>(up, smem, lds0, t0, nsw, t_max); break;
-            default: vb_run<8, false, true>(up, smem, lds0, t0, nsw, t_max); break;
+            case 1: vb_run<1, false, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 2: vb_run<2, false, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 4: vb_run<4, false, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+            default: vb_run<8, false, true, false>(up, smem, lds0, t0, nsw, t_max); break;
+        }
+    } else if (up->cpl) {
+        switch (up->rpad) {
+            case 1: vb_run<1, false, false, true>(up, smem, lds0, t0, nsw, t_max); break;
+            case 2: vb_run<2, false, false, true>(up, smem, lds0, t0, nsw, t_max); break;
+            case 4: vb_run<4, false, false, true>(up, smem, lds0, t0, nsw, t_max); break;
+            default: vb_run<8, false, false, true>(up, smem, lds0, t0, nsw, t_max); break;
         }
     } else {
         switch (up->rpad) {
-            case 1: vb_run<1, false, false>(up, smem, lds0, t0, nsw, t_max); break;
-            case 2: vb_run<2, false, false>(up, smem, lds0, t0, nsw, t_max); break;
-            case 4: vb_run<4, false, false>(up, smem, lds0, t0, nsw, t_max); break;
-            default: vb_run<8, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 1: vb_run<1, false, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 2: vb_run<2, false, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            case 4: vb_run<4, false, false, false>(up, smem, lds0, t0, nsw, t_max); break;
+            default: vb_run<8, false, false, false>(up, smem, lds0, t0, nsw, t_max); break;
         }
     }
 }
@@ -1048,12 +1075,24 @@ size_t vb_resident_bytes(int32_t n, int32_t m2)
     return ((size_t)(n + 1 + m2 + kVbEntPad) * 4 + 15) & ~(size_t)15;
 }
 
-size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads)
+size_t vb_lds_bytes(int32_t n, int32_t rpad, int32_t nch, int threads, bool cpl)
 {
     const size_t sw = (size_t)VbLayout(rpad).words(n);
     const size_t waves = (size_t)threads / 64;
-    return kSpOff + ((sw + 3) & ~(size_t)3) * 4 + (size_t)kVbMaxChains * kTab * 4 + kVbMaxChains * 8 + 16 +
+    return kSpOff + ((sw + 3) & ~(size_t)3) * 4 * (cpl ? 2 : 1) + (size_t)kVbMaxChains * kTab * 4 + kVbMaxChains * 8 + 16 +
            (kMaxCls + 4) * 4 + kVbMaxChains * 8 + (size_t)kMaxGrid * kVbMaxChains * 4 + waves * 64 * 16;
+}
+
+void vb_cpl_entries(const uint32_t* ent, size_t m, size_t pad, int32_t rpad, int32_t n, uint32_t* out)
+{
+    const VbLayout lay(rpad);
+    const uint32_t swp = ((uint32_t)lay.words(n) + 3u) & ~3u;
+    for (size_t e = 0; e < m + pad; ++e) {
+        const uint32_t en = e < m ? ent[e] : 0u;
+        const uint32_t pos = en & 0x7fffffffu;
+        const uint32_t addr = kSpOff + 4u * (pos / (uint32_t)lay.P) + ((en >> 31) != 0u ? 4u * swp : 0u);
+        out[e] = (addr << 5) | (pos % (uint32_t)lay.P);
+    }
 }
 
 hipError_t vb_init(const VbUnit* units, int n_units, int threads, size_t, hipStream_t s)

@@ -44,8 +44,10 @@ struct VbLayout {
 struct VbUnit {
     const int32_t* row;        // [n+1] adjacency row starts, sweep order
     const uint32_t* ent;       // [2m + kVbEntPad] neighbour position | (J < 0) << 31, then zeros
+    const uint32_t* entc;      // (cpl) the same entries in the form of vb_cpl_entries, read by the sweep
     const int32_t* cls;        // [ncls+1] first position of each colour class
     int32_t resident;          // 1: whole adjacency kept in LDS for the launch
+    int32_t cpl;               // 1: a complemented copy of the spin words is kept in LDS
     int32_t m2;                // 2m entries
     uint64_t key;              // Philox key (seed) shared by every chain of the unit
     uint32_t* state;           // [state_words] packed spins between launches

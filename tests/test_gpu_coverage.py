@@ -89,15 +89,19 @@ def oracle_all(descs, n_sweeps, t_max):
 PACKINGS = [(8, 4, 2), (7, 7, 1), (6, 3, 2), (5, 5, 1), (4, 2, 2), (2, 1, 2), (1, 1, 1)]
 
 
+# plain_lds: units that stream their adjacency keep no complemented copy of
+# the spin words (the sign of J is applied to the word read) instead of
+# addressing the copy
+@pytest.mark.parametrize("plain_lds", [False, True])
 @pytest.mark.parametrize("n", [3001, 40007])
 @pytest.mark.parametrize("cpu,n_inst,R", PACKINGS)
-def test_vb_high_degree_every_packing(n, cpu, n_inst, R):
+def test_vb_high_degree_every_packing(n, cpu, n_inst, R, plain_lds):
     require_gpu()
     e, J = hub_graph(n, 4.0, seed=n)
     temps = [0.9, 3.0, math.inf, 1.6, 0.5, 2.2, 0.0][:n_inst]
     descs = [sg.VbDesc(n=n, T=T, seed=21, instance_id=40 + k, edges=e, J=J, n_replicas=R)
              for k, T in enumerate(temps)]
-    res = run_lib(descs, [17, 23], 32, chains_per_unit=cpu)
+    res = run_lib(descs, [17, 23], 32, chains_per_unit=cpu, plain_lds=plain_lds)
     for i, ref in enumerate(oracle_all(descs, 40, 32)):
         assert_instance_equal(res, i, ref, label="n=%d cpu=%d inst %d" % (n, cpu, i))
 
