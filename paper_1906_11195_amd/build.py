@@ -4,6 +4,8 @@
 
 Every call recompiles all sources (in parallel) into
 ``paper_1906_11195_amd/_build/`` and links ``paper_1906_11195_amd/libsgmi.so``.
+``SG_BUILD_DEFINES`` (space-separated) adds compiler definitions, e.g.
+``SG_BUILD_DEFINES=-DSG_SK_PROF=1`` for the SK sweep's per-role cycle counters.
 """
 from __future__ import annotations
 
@@ -34,7 +36,7 @@ def _flags():
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
             # keep packed-FP32 instructions out of every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-function"]
+            "-Wall", "-Wno-unused-function"] + os.environ.get("SG_BUILD_DEFINES", "").split()
 
 
 def _compile(src: str) -> str:

@@ -64,6 +64,16 @@ constexpr int kThrCache = 512;      // threshold entries cached in LDS
 #ifndef SG_SK_UPB
 #define SG_SK_UPB 1
 #endif
+#ifndef SG_SK_PROF
+#define SG_SK_PROF 0    // 1: per-role cycle counters, printed by workgroups 0..2 after a launch
+#endif
+#if SG_SK_PROF
+#define SK_CLK(v) const unsigned long long v = clock64()
+#define SK_ACC(acc, a, b) (acc) += (b) - (a)
+#else
+#define SK_CLK(v)
+#define SK_ACC(acc, a, b)
+#endif
 constexpr int kUpdWaves = SG_SK_UPD;   // updater wavefronts
 constexpr int kUpdBlocks = SG_SK_UPB;  // decided blocks an updater pass takes at most
 static_assert(kUpdBlocks >= 1 && kUpdBlocks <= kRing, "updater pass width");
@@ -306,8 +316,16 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         auto delta = [](unsigned long long fp, unsigned long long fn, unsigned long long row) -> int32_t {
             return 2 * (__popcll(fp) - __popcll(fn)) - 4 * (__popcll(fp & row) - __popcll(fn & row));
         };
+#if SG_SK_PROF
+        // cycles waiting for the prep, reading its outputs, waiting for the
+        // updaters, correcting the fields, deciding, publishing; rounds
+        unsigned long long tp[7] = {0, 0, 0, 0, 0, 0, 0};
+#endif
         for (int64_t g = 0; g < total; ++g) {
+            SK_CLK(c0);
             wait_ge(L, kPrepared, (int32_t)(g + 1), err);
+            SK_CLK(c1);
+            SK_ACC(tp[0], c0, c1);
             // the prep's outputs and the spins (written by this wavefront
             // only) are read before waiting for the updaters
             const int32_t p = (b << 6) + lane;
@@ -316,7 +334,11 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             const uint32_t* tl = L.tile + ((size_t)slot * 64 + lane) * kTileWords;
             const unsigned long long D = ((unsigned long long)tl[1] << 32) | tl[0];   // own row, this block
             uint32_t sb = act ? (L.bits[p >> 5] >> (p & 31)) & 1u : 0u;
+            SK_CLK(c2);
+            SK_ACC(tp[1], c1, c2);
             if (g > DW) wait_applied(L, (int32_t)(g - DW), err);
+            SK_CLK(c3);
+            SK_ACC(tp[2], c2, c3);
             int32_t Hp = act ? L.H[p] : 0;
             // this block's fields still miss the flips of the previous DW
             // blocks (own row restricted to block b - d, d = 1..DW)
@@ -335,6 +357,8 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             // sequential result, in about three rounds).  The flips decided in
             // a round change the fields of the lanes after them at once; after
             // the last round every lane adds the flips after it.
+            SK_CLK(c4);
+            SK_ACC(tp[3], c3, c4);
             unsigned long long SB = __builtin_amdgcn_ballot_w64(sb != 0u);
             unsigned long long und = __builtin_amdgcn_ballot_w64(act);
             unsigned long long Fp = 0ull, Fn = 0ull;
@@ -361,10 +385,15 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
                     sb ^= 1u;
                 }
                 nf += __popcll(F);
+#if SG_SK_PROF
+                ++tp[6];
+#endif
                 SB ^= F;
                 Fp |= fp;
                 Fn |= fn;
             }
+            SK_CLK(c5);
+            SK_ACC(tp[4], c4, c5);
             Hp += delta(Fp & gt, Fn & gt, D);
 #pragma unroll
             for (int d = kWin - 1; d > 0; --d) {
@@ -383,6 +412,8 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             }
             wave_release();
             if (lane == 0) st_rel(&L.sync[kDecided], (int32_t)(g + 1));
+            SK_CLK(c6);
+            SK_ACC(tp[5], c5, c6);
             if (++slot == kRing) slot = 0;
             if (++b == NB) {
                 b = 0;
@@ -395,6 +426,12 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             }
         }
         if (lane == 0 && acc) atomicAdd(ch->accepted, (unsigned long long)acc);
+#if SG_SK_PROF
+        if (lane == 0 && blockIdx.x < 3)
+            printf("[sk-prof] wg %d decider blocks %lld cycles: wait-prep %llu reads %llu wait-updaters %llu "
+                   "correct %llu rounds %llu publish %llu; rounds %llu\n",
+                   (int)blockIdx.x, (long long)total, tp[0], tp[1], tp[2], tp[3], tp[4], tp[5], tp[6]);
+#endif
     } else {
         // ---------------- updaters ----------------
         // An updater lane owns items of 8 consecutive fields (one byte of a
@@ -411,8 +448,14 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
         const int32_t nitem = (n + 7) >> 3;
         const char* sprb = (const char*)L.spr;
         int32_t bk = 0, slot = 0;
+#if SG_SK_PROF
+        unsigned long long tu[2] = {0, 0};   // cycles waiting for decided blocks, applying them
+#endif
         for (int64_t k = 0; k < total;) {
+            SK_CLK(u0);
             wait_ge(L, kDecided, (int32_t)(k + 1), err);
+            SK_CLK(u1);
+            SK_ACC(tu[0], u0, u1);
             int32_t np = 1;
             if (kUpdBlocks > 1) {
                 const int32_t dec = __builtin_amdgcn_readfirstlane(ld_acq(&L.sync[kDecided]));
@@ -543,11 +586,17 @@ __global__ void __launch_bounds__(kSkThreads) sk_sweep_kernel(const SkChain* __r
             wave_release();
             k += np;
             if (lane == 0) st_rel(&L.sync[kProg + uw], (int32_t)k);
+            SK_CLK(u2);
+            SK_ACC(tu[1], u1, u2);
             slot += np;
             if (slot >= kRing) slot -= kRing;
             bk += np;
             while (bk >= NB) bk -= NB;
         }
+#if SG_SK_PROF
+        if (lane == 0 && blockIdx.x < 3)
+            printf("[sk-prof] wg %d updater %d cycles: wait %llu apply %llu\n", (int)blockIdx.x, uw, tu[0], tu[1]);
+#endif
     }
     __syncthreads();
 
