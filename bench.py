@@ -459,7 +459,8 @@ def run_serving(args, torch, sg, workloads):
     rng_len = [256, 512, 1024]
     for i, r in enumerate(reqs):
         r.sweeps = rng_len[i % 3]
-    server = serving.AgingServer(hbm_budget=64 << 30, max_active=64, chunk_sweeps=256, n_streams=8,
+    server = serving.AgingServer(hbm_budget=64 << 30, max_active=64, chunk_sweeps=256,
+                                 n_streams=SERVE_STREAMS,
                                  flags=sg.MEASURE_OBS)
     t0 = time.perf_counter()
     results = server.run(reqs, max_wall=120.0)
@@ -503,7 +504,8 @@ def run_serving_configured(args, torch, sg, workloads):
     base = workloads.serving_requests(n_req, rate=1.0)
 
     def serve(reqs, max_wall):
-        server = serving.AgingServer(hbm_budget=64 << 30, max_active=128, chunk_sweeps=4096, n_streams=8,
+        server = serving.AgingServer(hbm_budget=64 << 30, max_active=128, chunk_sweeps=4096,
+                                     n_streams=SERVE_STREAMS,
                                      flags=sg.MEASURE_OBS)
         t0 = time.perf_counter()
         out = server.run(reqs, max_wall=max_wall)
@@ -586,7 +588,20 @@ def run_cpu_baseline(args, workloads):
                        "one instance per thread (%d host CPUs visible); %.1f s" % (threads, sweeps, cores, el))
 
 
+# The serving legs keep a pool of SERVE_STREAMS streams, one per hardware
+# queue (streams sharing a queue run in submission order, so a batch would
+# wait for every batch enqueued before it on its queue): the process gets at
+# least that many hardware queues, set before HIP starts.
+SERVE_STREAMS = 8
+
+
 def main():
+    try:
+        hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+    except ValueError:
+        hwq = 4
+    if hwq < SERVE_STREAMS:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(SERVE_STREAMS)
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)

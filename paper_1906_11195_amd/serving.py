@@ -16,6 +16,7 @@ serving test checks exactly that.
 from __future__ import annotations
 
 import dataclasses
+import os
 import math
 import time
 from typing import Dict, List, Optional
@@ -24,6 +25,14 @@ import numpy as np
 
 from . import (MEASURE_OBS, MEASURE_SPINS, SkDesc, VbDesc, sg_create_sk, sg_create_vb, sg_free,
                sg_measure, sg_sweep)
+
+
+def hw_queues() -> int:
+    """Hardware queues per process that HIP maps streams onto."""
+    try:
+        return max(1, int(os.environ.get("GPU_MAX_HW_QUEUES", "4")))
+    except ValueError:
+        return 4
 
 
 def grid_len(t_max: int) -> int:
@@ -58,6 +67,8 @@ class Result:
     admitted: float
     finished: float
     obs: dict
+    built: float = 0.0      # the batch's context built and all its sweeps enqueued (host)
+    device: float = 0.0     # the batch's sweeps on its stream, first to last (HIP events)
 
     @property
     def latency(self) -> float:
@@ -120,11 +131,21 @@ class AgingServer:
     for the loop; new arrivals form the next batch on the next free stream
     while earlier ones run.  A batch is measured and released when its stream
     has finished; each request's result is its own slice of the batch's
-    observables, identical to the run alone."""
+    observables, identical to the run alone.
+
+    Streams beyond the process's hardware queues (HIP's GPU_MAX_HW_QUEUES,
+    4 unless set) share queues, and work on a shared queue runs in
+    submission order: a batch whose sweeps are all enqueued at admission
+    then holds back every batch queued behind it on the same queue.  So the
+    pool defaults to one stream per hardware queue (n_streams = None), and a
+    larger pool wants GPU_MAX_HW_QUEUES raised before the first HIP call."""
 
     def __init__(self, hbm_budget: int = 32 << 30, max_active: int = 64, chunk_sweeps: int = 256,
-                 n_streams: int = 4, flags: int = MEASURE_OBS | MEASURE_SPINS, max_batch: int = 64):
+                 n_streams: Optional[int] = None, flags: int = MEASURE_OBS | MEASURE_SPINS,
+                 max_batch: int = 64):
         import torch
+        if n_streams is None:
+            n_streams = hw_queues()
         self.torch = torch
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
@@ -139,24 +160,27 @@ class AgingServer:
 
     def _start(self, batch, stream):
         """Worker: builds the batch's context and enqueues all its sweeps on
-        `stream`; returns (context, completion event)."""
+        `stream`; returns (context, start event, completion event, host time
+        when everything was enqueued)."""
         torch = self.torch
         with torch.cuda.stream(stream):
             descs = [descriptor(r) for r in batch]
             make = sg_create_vb if batch[0].kind == "vb" else sg_create_sk
             ctx = make(descs, t_max=batch[0].sweeps)
             try:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
                 done, length = 0, batch[0].sweeps
                 while done < length:
                     k = min(self.chunk, length - done)
                     sg_sweep(ctx, k, stream=stream)
                     done += k
-                ev = torch.cuda.Event()
+                ev = torch.cuda.Event(enable_timing=True)
                 ev.record(stream)
             except BaseException:
                 sg_free(ctx)
                 raise
-        return ctx, ev
+        return ctx, ev0, ev, time.perf_counter()
 
     def run(self, requests, time_scale: float = 1.0, max_wall: Optional[float] = None) -> List[Result]:
         """Serves `requests` (arrival times in seconds from the start, scaled by
@@ -192,15 +216,16 @@ class AgingServer:
                 for b in list(batches):
                     if not b["fut"].done():
                         continue
-                    ctx, ev = b["fut"].result()
+                    ctx, ev0, ev, t_built = b["fut"].result()
                     if not ev.query():
                         continue
                     obs = sg_measure(ctx, self.flags, stream=self.streams[b["si"]])
                     sg_free(ctx)
                     fin = time.perf_counter() - t0
+                    dev = ev0.elapsed_time(ev) * 1e-3
                     for i, req in enumerate(b["reqs"]):
                         results.append(Result(req.rid, req.kind, req.n, req.sweeps, req.arrival * time_scale,
-                                              b["admitted"], fin, _slice(obs, i)))
+                                              b["admitted"], fin, _slice(obs, i), built=t_built - t0, device=dev))
                     used -= b["fp"]
                     free.append(b["si"])
                     batches.remove(b)
@@ -216,7 +241,7 @@ class AgingServer:
             # release what is still in flight (after a time limit or an error)
             for b in batches:
                 try:
-                    ctx, ev = b["fut"].result()
+                    ctx, _, ev, _ = b["fut"].result()
                 except BaseException:
                     continue
                 ev.synchronize()
@@ -239,8 +264,19 @@ def _slice(obs: dict, i: int) -> dict:
 
 
 def latency_stats(results: List[Result]) -> dict:
+    """p50 / p99 / mean latency, and where the mean goes: waiting for
+    admission (arrival to admission), the host build and enqueue of the
+    batch's context, the batch's sweeps on the device, and the rest (the
+    stream busy with other work before the sweeps start, completion polling,
+    measurement)."""
     lat = np.array([r.latency for r in results]) if results else np.zeros(0)
     if lat.size == 0:
         return dict(count=0)
+    queue = np.array([r.admitted - r.arrival for r in results])
+    build = np.array([max(0.0, r.built - r.admitted) for r in results])
+    device = np.array([r.device for r in results])
+    rest = lat - queue - build - device
     return dict(count=int(lat.size), p50_ms=float(np.percentile(lat, 50) * 1e3),
-                p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3))
+                p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                mean_split_ms=dict(queue=float(queue.mean() * 1e3), build=float(build.mean() * 1e3),
+                                   device=float(device.mean() * 1e3), rest=float(rest.mean() * 1e3)))
