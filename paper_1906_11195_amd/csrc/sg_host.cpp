@@ -395,6 +395,7 @@ struct sg_ctx {
     }
     int32_t count = 0, R = 0, K = 0, n_chains = 0;
     int64_t t_max = 0, t_done = 0;
+    int32_t bond_done = 0;   // VB: snapshots whose bond sums bond_d already holds
     // windowed correlation (VB): waiting times, intervals, sums per chain
     int32_t kw = 0, n_bins = 0;
     long long* win_d = nullptr;           // [n_chains][kw][n_bins]
@@ -1649,14 +1650,17 @@ void create_sk(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
 // Enqueues the measurement kernels of every grid time reached (kd of them)
 // on stream s: bond sums into bond[chains][K] (SK: 2 B, halved by the
 // caller), overlaps into overlap[pairs][K], Gram matrices into
-// gram[chains][K][K] (zeroed first: the kernel accumulates).
-void enqueue_obs(sg_ctx* c, int32_t kd, long long* bond, long long* overlap, long long* gram, hipStream_t s)
+// gram[chains][K][K] (zeroed first: the kernel accumulates).  VB bond sums
+// of the snapshots before k_first are taken as already in `bond` (a
+// snapshot never changes once written).
+void enqueue_obs(sg_ctx* c, int32_t kd, long long* bond, long long* overlap, long long* gram, hipStream_t s,
+                 int32_t k_first = 0)
 {
     const int32_t K = c->K;
     if (c->kind == 0) {
-        hip_check(vb_bond(c->units_d, (int)c->units.size(), kd, bond, c->unit_chain_ids_d, K,
+        hip_check(vb_bond(c->units_d, (int)c->units.size(), k_first, kd, bond, c->unit_chain_ids_d, K,
                           std::min(1024, c->vb_threads), c->bond_lds, s));
-        hip_check(vbm_bond(c->vbm_d, (int)c->vbm.size(), kd, bond, c->vbm_ids_d, K, s));
+        hip_check(vbm_bond(c->vbm_d, (int)c->vbm.size(), k_first, kd, bond, c->vbm_ids_d, K, s));
     } else if (c->sk_real) {
         hip_check(zero_i64(bond, (size_t)c->n_chains * K, s));
         hip_check(skg_bond(c->sks_d, c->count, c->sk_d, c->sk_max_n, c->R, kd, K, c->bpart_d, c->bondr_d, s));
@@ -1875,7 +1879,8 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
         out->k_done = kd;
         out->t_done = c->t_done;
         if (flags & SG_MEASURE_OBS) {
-            enqueue_obs(c, kd, c->bond_d, c->overlap_d, c->gram_d, s);
+            // the context's bond array keeps the sums of earlier measurements
+            enqueue_obs(c, kd, c->bond_d, c->overlap_d, c->gram_d, s, c->kind == 0 ? c->bond_done : 0);
             std::vector<long long> bond((size_t)c->n_chains * K), ovl((size_t)std::max(1, c->n_pairs) * K),
                 gram((size_t)c->n_chains * K * K);
             std::vector<unsigned long long> acc((size_t)c->n_chains);
@@ -1888,6 +1893,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
             window_out(c, out, s);
             bond_real_out(c, out, s);
             hip_check(hipStreamSynchronize(s));
+            c->bond_done = kd;
             bond_real_finish(c, out, kd);
             if (out->times)
                 for (int32_t k = 0; k < K; ++k) out->times[k] = c->times[(size_t)k];

@@ -111,10 +111,10 @@ hipError_t vbm_init(const VbmUnit* units, int n_units, hipStream_t s);
 hipError_t vbm_prepare();
 hipError_t vbm_sweep(const VbmUnit* units, int n_units, int threads, size_t lds_bytes, const int64_t* t0p,
                      int32_t n_sweeps, int64_t t_max, hipStream_t s);
-// bond sums of the snapshots of every chain of every unit: out[chain][k],
-// chain ids [unit][64]
-hipError_t vbm_bond(const VbmUnit* units, int n_units, int k_done, long long* out, const int32_t* chain_ids,
-                    int k_cap, hipStream_t s);
+// bond sums of the snapshots k_first .. k_done - 1 of every chain of every
+// unit: out[chain][k], chain ids [unit][64]
+hipError_t vbm_bond(const VbmUnit* units, int n_units, int k_first, int k_done, long long* out,
+                    const int32_t* chain_ids, int k_cap, hipStream_t s);
 
 // err_flag bit 0: recompute mismatch; bit 1: the sweep pipeline stalled.
 hipError_t sk_init(const SkChain* chains, int n_chains, int threads, hipStream_t s);
@@ -143,7 +143,9 @@ hipError_t skg_recompute(const SkSample* samples, int n_samples, const SkChain* 
 hipError_t skg_bond(const SkSample* samples, int n_samples, const SkChain* chains, int max_n, int max_nch,
                     int k_done, int k_cap, double* part, double* out, hipStream_t s);
 
-hipError_t vb_bond(const VbUnit* units, int n_units, int k_done, long long* bond_out,
+// bond sums of the snapshots k_first .. k_done - 1 of every chain:
+// bond_out[chain][k] (the other entries are left as they are)
+hipError_t vb_bond(const VbUnit* units, int n_units, int k_first, int k_done, long long* bond_out,
                    const int32_t* unit_chain_ids, int k_cap, int threads, size_t lds_bytes,
                    hipStream_t s);
 hipError_t measure_overlap(const MeasureChain* chains, const int32_t* pairs, int n_pairs,

@@ -106,12 +106,12 @@ __global__ void __launch_bounds__(256) overlap_kernel(const MeasureChain* __rest
 // counts each edge twice.
 __global__ void __launch_bounds__(1024) vb_bond_kernel(const VbUnit* __restrict__ units,
                                                        const int32_t* __restrict__ chain_ids,
-                                                       int k_cap, long long* __restrict__ out)
+                                                       int k_first, int k_cap, long long* __restrict__ out)
 {
     extern __shared__ uint32_t bsm[];
     const VbUnit* up = units + blockIdx.x;
     if (up->member != 0) return;   // a split unit is measured once
-    const int k = blockIdx.y;
+    const int k = k_first + (int)blockIdx.y;
     const int32_t n = up->n, wn = up->words_n, nch = up->nch;
     long long* red = (long long*)(bsm + ((nch * wn + 1) & ~1));
     for (int32_t idx = threadIdx.x; idx < nch * wn; idx += blockDim.x) {
@@ -209,17 +209,17 @@ hipError_t measure_overlap(const MeasureChain* chains, const int32_t* pairs, int
     return hipGetLastError();
 }
 
-hipError_t vb_bond(const VbUnit* units, int n_units, int k_done, long long* bond_out,
+hipError_t vb_bond(const VbUnit* units, int n_units, int k_first, int k_done, long long* bond_out,
                    const int32_t* unit_chain_ids, int k_cap, int threads, size_t lds_bytes,
                    hipStream_t s)
 {
-    if (n_units <= 0 || k_done <= 0) return hipSuccess;
+    if (n_units <= 0 || k_done <= k_first) return hipSuccess;
     // set once (thread-safe initialisation of a local static)
     static const hipError_t attr = hipFuncSetAttribute((const void*)vb_bond_kernel,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(vb_bond_kernel, dim3(n_units, k_done), dim3(threads), lds_bytes, s, units,
-                       unit_chain_ids, k_cap, bond_out);
+    hipLaunchKernelGGL(vb_bond_kernel, dim3(n_units, k_done - k_first), dim3(threads), lds_bytes, s, units,
+                       unit_chain_ids, k_first, k_cap, bond_out);
     return hipGetLastError();
 }
 

@@ -282,16 +282,16 @@ __global__ void __launch_bounds__(256) vbm_init_kernel(const VbmUnit* __restrict
 // adjacency entry gives the unsatisfied bonds of all chains as one XOR,
 // counted in a bit-sliced counter per thread.  Each edge is two directed
 // entries, so per chain B = (entries - 2 unsatisfied entries) / 2.
-// grid = (units, k_done), 256 threads, n 64-bit words of dynamic LDS.
+// grid = (units, k_done - k_first), 256 threads, n 64-bit words of dynamic LDS.
 __global__ void __launch_bounds__(256) vbm_bond_kernel(const VbmUnit* __restrict__ units,
-                                                       const int32_t* __restrict__ chain_ids, int k_cap,
-                                                       long long* __restrict__ out)
+                                                       const int32_t* __restrict__ chain_ids, int k_first,
+                                                       int k_cap, long long* __restrict__ out)
 {
     extern __shared__ __attribute__((aligned(16))) uint64_t bw[];
     __shared__ unsigned long long uns[kVbmChains];
     __shared__ unsigned long long ents;
     const VbmUnit* up = units + blockIdx.x;
-    const int k = blockIdx.y;
+    const int k = k_first + (int)blockIdx.y;
     const int32_t n = up->n, wn = up->words_n, nch = up->nch;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, W = blockDim.x >> 6;
     if (tid < kVbmChains) uns[tid] = 0ull;
@@ -376,13 +376,13 @@ hipError_t vbm_sweep(const VbmUnit* units, int n_units, int threads, size_t lds_
     return hipGetLastError();
 }
 
-hipError_t vbm_bond(const VbmUnit* units, int n_units, int k_done, long long* out, const int32_t* chain_ids,
-                    int k_cap, hipStream_t s)
+hipError_t vbm_bond(const VbmUnit* units, int n_units, int k_first, int k_done, long long* out,
+                    const int32_t* chain_ids, int k_cap, hipStream_t s)
 {
-    if (n_units <= 0 || k_done <= 0) return hipSuccess;
+    if (n_units <= 0 || k_done <= k_first) return hipSuccess;
     // one 64-bit word per position of the largest unit (n <= kVbmMaxN)
-    hipLaunchKernelGGL(vbm_bond_kernel, dim3(n_units, k_done), dim3(256), (size_t)kVbmMaxN * 8, s, units,
-                       chain_ids, k_cap, out);
+    hipLaunchKernelGGL(vbm_bond_kernel, dim3(n_units, k_done - k_first), dim3(256), (size_t)kVbmMaxN * 8, s,
+                       units, chain_ids, k_first, k_cap, out);
     return hipGetLastError();
 }
 
