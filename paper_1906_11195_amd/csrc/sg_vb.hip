@@ -559,18 +559,7 @@ __device__ void vb_snapshot(const VbUnit* __restrict__ up, const uint32_t* __res
     }
 }
 
-// Windowed correlation (the paper's estimator: C(t_w + t, t_w) averaged over
-// minor-third intervals of t_w + t, ratio 2^(1/4); Results and discussion,
-// and the SI section on the extrapolation to large sizes and times), at the
-// end of the sweep that ends at time tau <= t_max: for every stored waiting
-// time t_w < tau and every chain, the overlap sum_i s_i(tau) s_i(t_w) =
-// n - 2 popcount(s(tau) xor s(t_w)) over the chain's fields, added to the
-// chain's sum for the interval of tau.  The spin words at the waiting times
-// are stored in the same sliced packing as the LDS words, so one XOR and a
-// masked popcount per word and chain count every chain.  Each thread counts
-// (and, at the waiting times, stores) the words w = tid + member * threads
-// (mod members * threads): the members of a split unit count disjoint words
-// and no thread reads another's stores.
+// cnt[c] += the set bits of d in chain c's field (chains c < nch)
 template <int RPAD>
 __device__ __forceinline__ void win_count(uint32_t* cnt, uint32_t d, int32_t nch)
 {
@@ -583,14 +572,39 @@ __device__ __forceinline__ void win_count(uint32_t* cnt, uint32_t d, int32_t nch
 
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
+// Adds the four words of d ^ e, bit by bit, to the bit-sliced counters
+// (ones, twos) of a thread, and the carries of weight 4 to the per-chain
+// counts cnt4 (carry-save adders: sum = a ^ b ^ c, carry = majority): one
+// masked popcount per chain for four words instead of four.
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) { return (a & b) | (c & (a | b)); }
+
 template <int RPAD>
-__device__ __forceinline__ void win_count4(uint32_t* cnt, v4u a, v4u b, int32_t nch)
+__device__ __forceinline__ void win_add4(uint32_t& ones, uint32_t& twos, uint32_t* cnt4, v4u a, v4u b, int32_t nch)
 {
     const v4u d = a ^ b;
-    win_count<RPAD>(cnt, d.x, nch);
-    win_count<RPAD>(cnt, d.y, nch);
-    win_count<RPAD>(cnt, d.z, nch);
-    win_count<RPAD>(cnt, d.w, nch);
+    const uint32_t h1 = maj3(ones, d.x, d.y);
+    ones ^= d.x ^ d.y;
+    const uint32_t h2 = maj3(ones, d.z, d.w);
+    ones ^= d.z ^ d.w;
+    const uint32_t f = maj3(twos, h1, h2);
+    twos ^= h1 ^ h2;
+    win_count<RPAD>(cnt4, f, nch);
+}
+
+// cnt = 4 cnt4 + the counts of the planes (ones, twos), per chain
+template <int RPAD>
+__device__ __forceinline__ void win_fold(uint32_t* cnt, uint32_t ones, uint32_t twos, int32_t nch)
+{
+    uint32_t c1[RPAD], c2[RPAD];
+#pragma unroll
+    for (int c = 0; c < RPAD; ++c) {
+        c1[c] = 0u;
+        c2[c] = 0u;
+    }
+    win_count<RPAD>(c1, ones, nch);
+    win_count<RPAD>(c2, twos, nch);
+#pragma unroll
+    for (int c = 0; c < RPAD; ++c) cnt[c] = 4u * cnt[c] + c1[c] + 2u * c2[c];
 }
 
 // Windowed correlation (the paper's estimator: C(t_w + t, t_w) averaged over
@@ -601,8 +615,10 @@ __device__ __forceinline__ void win_count4(uint32_t* cnt, v4u a, v4u b, int32_t 
 // n - 2 popcount(s(tau) xor s(t_w)) over the chain's fields, added to the
 // chain's sum for the interval of tau.  The spin words at the waiting times
 // are stored in the same sliced packing as the LDS words (rows of `ws4`
-// 16-byte groups; the words past state_words are zero on both sides), so one
-// XOR and a masked popcount per word and chain count every chain.  The
+// 16-byte groups; the words past state_words are zero on both sides), so the
+// XOR of two words holds every chain's disagreements; a thread adds them up
+// bit-sliced (carry-save adders) and counts the chains' fields of the carry
+// planes.  The
 // stored words are streamed from HBM with 16-byte loads, four groups of two
 // waiting times in flight per lane.  Each thread counts (and, at the waiting
 // times, stores) the groups i = tid + member * threads (mod members *
@@ -638,6 +654,7 @@ __device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ u
             c0[c] = 0u;
             c1[c] = 0u;
         }
+        uint32_t on0 = 0u, tw0 = 0u, on1 = 0u, tw1 = 0u;   // bit-sliced counters
         for (int32_t i0 = w0; i0 < sw4; i0 += U * stride) {
             v4u a[U], b0[U], b1[U];
 #pragma unroll
@@ -650,10 +667,12 @@ __device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ u
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                win_count4<RPAD>(c0, a[u], b0[u], nch);
-                if (two) win_count4<RPAD>(c1, a[u], b1[u], nch);
+                win_add4<RPAD>(on0, tw0, c0, a[u], b0[u], nch);
+                if (two) win_add4<RPAD>(on1, tw1, c1, a[u], b1[u], nch);
             }
         }
+        win_fold<RPAD>(c0, on0, tw0, nch);
+        win_fold<RPAD>(c1, on1, tw1, nch);
 #pragma unroll
         for (int c = 0; c < RPAD; ++c) {
             if (c < nch) {
