@@ -3,7 +3,8 @@
 Covers several samples with two clones through field recomputations, ragged
 sizes (not multiples of the 64-spin block or of 16), T = inf and T = 0,
 aligned and given starts, given couplings, sweeps split over calls, and the
-full-size SK configuration on a prefix of sweeps with sampled chains."""
+full-size SK configuration on a prefix of sweeps with sampled chains, and
+the largest supported sizes."""
 import math
 
 import numpy as np
@@ -90,3 +91,14 @@ def test_sk_full_size_prefix_sampled():
     for i in (0, 37, 63):
         assert_instance_equal(res, i, oracle_sk(descs[i], 65, workloads.SK_SWEEPS), spins=False,
                               label="sample %d" % i)
+
+
+@pytest.mark.parametrize("n", [16384, 32768])
+def test_sk_largest_sizes(n):
+    # The largest binary sizes: the fields fill most of the workgroup's LDS
+    # (128 KiB at N = 32768), each coupling row spans 2-4 KiB, and the first
+    # sweeps from a random start flip many spins per block.
+    require_gpu()
+    d = sg.SkDesc(n=n, T=0.5, seed=5, instance_id=0, graph_id=5, recompute_period=4)
+    res = run_lib([d], 6, 8)
+    assert_instance_equal(res, 0, oracle_sk(d, 6, 8), label="n=%d" % n)
