@@ -187,7 +187,24 @@ typedef void (*sg_free_fn)(void* ptr, size_t bytes, void* user);
  *                   k workgroups for every unit with at least 2 k chunks of
  *                   64 positions per wavefront in its largest colour class.
  *                   Has no effect on any result; a barrier that times out
- *                   (20 s) makes sg_measure return SG_EDEVICE. */
+ *                   (20 s) makes sg_measure return SG_EDEVICE.
+ *  t_start          resume (0 = a new run): the time, 0 <= t_start < 2^32,
+ *                   of the start configurations the descriptors pass
+ *                   (SG_START_GIVEN, typically the spins sg_measure exported
+ *                   from a run at that time).  The sweep counter starts at
+ *                   t_start, so every random stream (counter-based, keyed by
+ *                   the sweep index; Methods) continues where that run
+ *                   stopped and the sweeps from t_start on are those of one
+ *                   uninterrupted run, bit for bit.  Snapshot slot 0 then
+ *                   holds the start configuration (times[0] = t_start); the
+ *                   slots of grid times <= t_start are not taken (times[k] =
+ *                   -1, their entries 0); accepted counts the flips since
+ *                   t_start.  Not with SG_OPT_WINDOW (SG_ENOTSUP; the
+ *                   waiting-time configurations before t_start are not
+ *                   kept).  Real SK couplings: t_start must be a multiple of
+ *                   the recompute period (the fields are then the exact
+ *                   direct sums the uninterrupted run also has), else
+ *                   SG_EINVAL. */
 typedef struct sg_opts {
     int64_t t_max;
     sg_alloc_fn alloc;
@@ -198,6 +215,7 @@ typedef struct sg_opts {
     uint32_t flags;
     int32_t split_members;
     int64_t window_tw_max;
+    int64_t t_start;
 } sg_opts;
 
 /* sg_opts.flags (VB contexts; AUTOTUNE and GRAPH have no effect on any result) */
@@ -247,7 +265,8 @@ typedef struct sg_opts {
  *                      (lexicographic);
  *   gram[i][r][k][l]   sum_u s_u(t_k) s_u(t_l), so C(t_k, t_l) = gram / N;
  *   accepted[i][r]     accepted flips so far.
- * Entries for grid times not reached yet are 0.  spins holds, for each
+ * Entries for grid times not reached yet, and for slots not taken after a
+ * resume (times[k] = -1, see sg_opts.t_start), are 0.  spins holds, for each
  * instance in order, n_replicas rows of n int8 +-1 in vertex order. */
 typedef struct sg_obs {
     int32_t count;

@@ -55,7 +55,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("t_max", ctypes.c_int64), ("alloc", _ALLOC_FN), ("free", _FREE_FN),
                 ("user", ctypes.c_void_p), ("chains_per_unit", ctypes.c_int32),
                 ("threads_per_unit", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("split_members", ctypes.c_int32), ("window_tw_max", ctypes.c_int64)]
+                ("split_members", ctypes.c_int32), ("window_tw_max", ctypes.c_int64),
+                ("t_start", ctypes.c_int64)]
 
 
 class _Obs(ctypes.Structure):
@@ -225,9 +226,10 @@ _FREE_CB = _FREE_FN(_torch_free)
 
 
 def _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags=0, split_members=0,
-          window_tw_max=0):
+          window_tw_max=0, t_start=0):
     o = _Opts()
     o.t_max = int(t_max)
+    o.t_start = int(t_start)
     o.window_tw_max = int(window_tw_max)
     o.chains_per_unit = int(chains_per_unit)
     o.threads_per_unit = int(threads_per_unit)
@@ -286,11 +288,12 @@ def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
                  threads_per_unit: int = 0, torch_alloc: bool = True, autotune: bool = False,
                  graph: bool = False, split_members: int = 0,
                  window_tw_max: Optional[int] = None, multispin: bool = False,
-                 plain_lds: bool = False) -> Context:
+                 plain_lds: bool = False, t_start: int = 0) -> Context:
     """window_tw_max: measure the windowed correlation with the grid times
     <= window_tw_max as waiting times (SG_OPT_WINDOW); multispin: pack the
     chains of a shared graph 64 per word (SG_OPT_MULTISPIN); plain_lds: keep
-    no complemented copy of the spin words (SG_OPT_PLAIN_LDS)."""
+    no complemented copy of the spin words (SG_OPT_PLAIN_LDS); t_start:
+    resume from start configurations at that time (sg_opts.t_start)."""
     keep = []
     arr = (_VbDesc * len(descs))(*[_vb_struct(d, keep) for d in descs])
     flags = (OPT_AUTOTUNE if autotune else 0) | (OPT_GRAPH if graph else 0)
@@ -302,7 +305,7 @@ def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
         kw = _grid_len(min(int(window_tw_max), int(t_max)))   # grid times <= window_tw_max
         n_bins = (int(t_max) ** 4).bit_length()                # intervals of 1 .. t_max
     o = _opts(t_max, chains_per_unit, threads_per_unit, torch_alloc, flags, split_members,
-              window_tw_max if window_tw_max is not None else 0)
+              window_tw_max if window_tw_max is not None else 0, t_start)
     out = ctypes.c_void_p()
     _check(library().sg_create_vb(ctypes.byref(arr), len(descs), ctypes.byref(o), ctypes.byref(out)),
            "sg_create_vb")
@@ -310,10 +313,11 @@ def sg_create_vb(descs: Sequence[VbDesc], t_max: int, chains_per_unit: int = 0,
 
 
 def sg_create_sk(descs: Sequence[SkDesc], t_max: int, threads_per_unit: int = 0,
-                 torch_alloc: bool = True) -> Context:
+                 torch_alloc: bool = True, t_start: int = 0) -> Context:
+    """t_start: resume from start configurations at that time (sg_opts.t_start)."""
     keep = []
     arr = (_SkDesc * len(descs))(*[_sk_struct(d, keep) for d in descs])
-    o = _opts(t_max, 0, threads_per_unit, torch_alloc)
+    o = _opts(t_max, 0, threads_per_unit, torch_alloc, t_start=t_start)
     out = ctypes.c_void_p()
     _check(library().sg_create_sk(ctypes.byref(arr), len(descs), ctypes.byref(o), ctypes.byref(out)),
            "sg_create_sk")

@@ -395,6 +395,7 @@ struct sg_ctx {
     }
     int32_t count = 0, R = 0, K = 0, n_chains = 0;
     int64_t t_max = 0, t_done = 0;
+    int64_t t_start = 0;                  // time of the start configurations (resume)
     int32_t bond_done = 0;   // VB: snapshots whose bond sums bond_d already holds
     // windowed correlation (VB): waiting times, intervals, sums per chain
     int32_t kw = 0, n_bins = 0;
@@ -516,9 +517,14 @@ void setup_common(sg_ctx* c, const sg_opts* o)
 {
     c->t_max = o ? o->t_max : 0;
     if (c->t_max < 0 || c->t_max >= (int64_t)1 << 31) fail(SG_EINVAL);
+    c->t_start = o ? o->t_start : 0;
+    if (c->t_start < 0 || c->t_start >= (int64_t)1 << 32) fail(SG_EINVAL);
+    c->t_done = c->t_start;
     c->K = grid_size(c->t_max);
-    c->times.push_back(0);
-    for (int64_t t = 1; t <= c->t_max; t <<= 1) c->times.push_back(t);
+    // slot 0: the start configuration; slot k >= 1: grid time 2^(k-1), not
+    // taken (-1) when it is not after t_start
+    c->times.push_back(c->t_start);
+    for (int64_t t = 1; t <= c->t_max; t <<= 1) c->times.push_back(t > c->t_start ? t : -1);
     if (o) {
         c->alloc = o->alloc;
         c->freef = o->free;
@@ -530,6 +536,7 @@ void setup_common(sg_ctx* c, const sg_opts* o)
         if (o->chains_per_unit < 0 || o->chains_per_unit > kVbMaxChains) fail(SG_EINVAL);
         if (o->flags & SG_OPT_WINDOW) {
             if (c->t_max < 1 || o->window_tw_max < 0) fail(SG_EINVAL);
+            if (c->t_start > 0) fail(SG_ENOTSUP);
             c->kw = 0;
             for (int64_t t : c->times)
                 if (t <= o->window_tw_max) ++c->kw;
@@ -1275,6 +1282,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     hip_check(zero_i64(c->bond_d, (size_t)c->n_chains * c->K, nullptr));
     hip_check(zero_i64((long long*)c->acc_d, (size_t)c->n_chains, nullptr));
     hip_check(zero_i64((long long*)c->t_dev, 2, nullptr));
+    if (c->t_start > 0) hip_check(hipMemcpy(c->t_dev, &c->t_start, 8, hipMemcpyHostToDevice));
     hip_check(zero_i64((long long*)c->bars_d, (size_t)std::max(1, n_split), nullptr));
     hip_check(zero_i64((long long*)c->err_d, 1, nullptr));
     hip_check(vb_init(c->units_d, (int)c->units.size(), 256, 0, nullptr));
@@ -1310,6 +1318,9 @@ void create_skg(sg_ctx* c, const sg_sk_desc* d, int32_t count, const sg_opts* o)
     }
     setup_common(c, o);
     if (c->kw > 0) fail(SG_ENOTSUP);   // the windowed correlation is measured for VB only
+    // a resume is exact when the fields start from the direct sums the
+    // uninterrupted run also recomputes at that time
+    if (c->t_start % c->period != 0) fail(SG_EINVAL);
     c->n_chains = count * c->R;
     c->n_of.resize((size_t)count);
     // instances passing the same array share its device copy
@@ -1730,6 +1741,29 @@ void bond_real_finish(sg_ctx* c, sg_obs* out, int32_t kd)
         if ((int32_t)(i % c->K) >= kd) out->bond_real[i] = 0.0;
 }
 
+// After a resume (t_start > 0): the entries of the slots not taken (grid
+// times not after t_start, times[k] = -1) are 0.  Their snapshot memory was
+// never written, so whatever the measurement kernels made of it is dropped.
+void mask_untaken(const sg_ctx* c, sg_obs* out)
+{
+    if (c->t_start == 0) return;
+    const size_t K = (size_t)c->K;
+    for (size_t k = 0; k < K; ++k) {
+        if (c->times[k] >= 0) continue;
+        for (size_t ch = 0; ch < (size_t)c->n_chains; ++ch) {
+            if (out->bond) out->bond[ch * K + k] = 0;
+            if (out->bond_real && c->sk_real) out->bond_real[ch * K + k] = 0.0;
+            if (out->gram)
+                for (size_t l = 0; l < K; ++l) {
+                    out->gram[(ch * K + k) * K + l] = 0;
+                    out->gram[(ch * K + l) * K + k] = 0;
+                }
+        }
+        if (out->overlap)
+            for (size_t p = 0; p < (size_t)c->n_pairs; ++p) out->overlap[p * K + k] = 0;
+    }
+}
+
 // Status of a measurement from the context's error word.
 sg_status status_of_flag(int err_flag)
 {
@@ -1907,6 +1941,7 @@ sg_status sg_measure(sg_ctx* c, uint32_t flags, sg_obs* out, void* stream)
                 for (size_t i = 0; i < gram.size(); ++i) out->gram[i] = (int64_t)gram[i];
             if (out->accepted)
                 for (size_t i = 0; i < acc.size(); ++i) out->accepted[i] = (int64_t)acc[i];
+            mask_untaken(c, out);
         }
         if ((flags & SG_MEASURE_SPINS) && out->spins) {
             hip_check(hipStreamSynchronize(s));
@@ -2012,6 +2047,7 @@ sg_status sg_measure_noalloc(sg_ctx* c, sg_obs* out, void* stream)
         if (out->overlap)
             for (size_t i = 0; i < n_ovl; ++i)
                 if ((int64_t)(i % K) >= kd) out->overlap[i] = 0;
+        mask_untaken(c, out);
     });
     if (st != SG_OK) return st;
     return status_of_flag(err_flag);

@@ -140,3 +140,15 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(sg.SgError) as e:
         sg.sg_create_vb([sg.VbDesc(n=64, T=1.0, seed=1, instance_id=0)], t_max=4, torch_alloc=False)
     assert e.value.code == sg.SG_EDEVICE
+
+
+def test_resume_options_checked_before_the_device():
+    # sg_opts.t_start: 0 <= t_start < 2^32, and no windowed correlation
+    d = [sg.VbDesc(n=64, T=1.0, seed=1, instance_id=0)]
+    for ts in (-1, 1 << 32):
+        with pytest.raises(sg.SgError) as e:
+            sg.sg_create_vb(d, t_max=4, torch_alloc=False, t_start=ts)
+        assert e.value.code == sg.SG_EINVAL
+    with pytest.raises(sg.SgError) as e:
+        sg.sg_create_vb(d, t_max=4, torch_alloc=False, t_start=2, window_tw_max=1)
+    assert e.value.code == sg.SG_ENOTSUP
