@@ -61,6 +61,42 @@ def test_vb_transient_energy_matches_master_equation(T):
         assert abs(z) < 5.0, (t, bonds[:, k].mean(), mean_exact, z)
 
 
+def test_order_inside_a_colour_class_does_not_change_the_law():
+    # The reading that visits each colour class by decreasing degree (then
+    # id): the spins of a class are pairwise unconnected, so their single-spin
+    # updates commute and the one-sweep transition operator (the law of the
+    # dynamics, Eq. 3 with the Metropolis rule) is the same for every order
+    # inside the classes.  The operator for the oracle's order equals the
+    # one for id order and for random in-class permutations, column by column
+    # (each basis state propagated exactly); changing the order of the classes
+    # does change it (control).
+    n, T = 8, 0.9
+    eu, ev, J = _ring_with_chords(n, seed=5)
+    A = brute.coupling_matrix(n, eu, ev, J)
+    S = brute.states(n)
+    colour, ncol = oracle.greedy_colour(n, eu, ev)
+    assert ncol >= 3
+    assert np.all(colour[eu] != colour[ev])
+
+    def operator(order):
+        cols = []
+        for s0 in range(1 << n):
+            e = np.zeros(1 << n)
+            e[s0] = 1.0
+            cols.append(brute.sweep(e, S, A, list(order), T))
+        return np.stack(cols, axis=1)
+
+    base = operator(oracle.sweep_order(colour, ncol, oracle.degrees(n, eu, ev)))
+    assert np.allclose(base.sum(axis=0), 1.0, atol=1e-12)
+    assert np.allclose(operator(sorted(range(n), key=lambda v: (colour[v], v))), base, atol=1e-13)
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        perm = sorted(range(n), key=lambda v: (colour[v], rng.random()))
+        assert np.allclose(operator(perm), base, atol=1e-13)
+    reversed_classes = sorted(range(n), key=lambda v: (-colour[v], v))
+    assert not np.allclose(operator(reversed_classes), base, atol=1e-6)
+
+
 def test_vb_equilibrium_is_boltzmann():
     # Long runs sample the Boltzmann distribution exp(-H/T) (Eq. 3 with the
     # Metropolis rule); compare state frequencies by chi^2 and check pi P = pi.
