@@ -12,11 +12,13 @@
 // edge's coupling word: bit c is set where chain c's bond is unsatisfied, and
 // a bit-sliced counter (4 bit planes, 6 when a degree in the chunk exceeds
 // 15) counts them for all 64 chains at once.  The decisions are then taken
-// chain by chain: the counts of 8 chains are gathered into one word of
-// nibbles, x = deg - 2 count indexes the chain's threshold table (high 16
-// bits, 65536 for x <= 0), and the high half-word A of the chain's uniform is
-// compared with it; a tie (probability 2^-16) is settled on the low halves as
-// in the per-chain layout.  The Philox blocks of 8 chains are drawn per pass,
+// chain by chain: the bit planes of 8 chains' counts are spread to bytes and
+// combined into the byte offsets of the chains' entries x = deg - 2 count in
+// their threshold tables (high 16 bits, 65536 for x <= 0), and the high
+// half-word A of the chain's uniform is compared with it by the sign of the
+// difference; a tie (probability 2^-16) is settled on the low halves as in
+// the per-chain layout.  The adjacency is prefetched along the wavefront's
+// chunk sequence (rows two chunks ahead, the first entries one ahead).  The Philox blocks of 8 chains are drawn per pass,
 // one per lane, and exchanged through LDS.  Each lane owns its position's
 // word, so the flips are written back with a plain XOR.
 #include "sg_internal.h"
@@ -26,7 +28,7 @@ namespace sg {
 namespace {
 
 constexpr int kMaxClsM = 64;   // colour classes (degree <= 63)
-constexpr int kThrSpan = 32;   // LDS threshold entries per chain: x = -15 .. 15 (index x + 16)
+constexpr int kThrSpan = 32;   // LDS threshold entries per chain: x = 15 .. -16 (index 15 - x)
 
 __device__ __forceinline__ void wave_sync_m()
 {
@@ -37,11 +39,12 @@ __device__ __forceinline__ void wave_sync_m()
 
 struct VbmLds {
     uint64_t* sp;                 // [n] spin words
-    uint32_t* thr;                // [64][kThrSpan]: chain c, x + 16 -> thr[x] >> 16; 65536 for x <= 0
+    uint32_t* thr;                // [64][kThrSpan]: chain c, 15 - x -> thr[x] >> 16; 65536 for x <= 0
     uint32_t* ri;                 // [64][2]: replica, instance
     int32_t* cls;                 // [kMaxClsM + 4]
     unsigned long long* acc;      // [64] accepted flips of the launch
     uint4* xch;                   // [waves][64] Philox blocks of 8 chains
+    unsigned long long* spr8;     // [256]: bit j of the index -> byte j
 };
 
 __device__ __forceinline__ VbmLds vbm_carve(uint8_t* base, int32_t n, int waves)
@@ -59,25 +62,8 @@ __device__ __forceinline__ VbmLds vbm_carve(uint8_t* base, int32_t n, int waves)
     L.cls = (int32_t*)take((size_t)(kMaxClsM + 4) * 4);
     L.acc = (unsigned long long*)take((size_t)kVbmChains * 8);
     L.xch = (uint4*)take((size_t)waves * 64 * 16);
+    L.spr8 = (unsigned long long*)take(256 * 8);
     return L;
-}
-
-// bit i (i < 8) of x -> bit 4 i
-__device__ __forceinline__ uint32_t spread8(uint32_t x)
-{
-    x &= 0xffu;
-    x = (x | (x << 12)) & 0x000F000Fu;
-    x = (x | (x << 6)) & 0x03030303u;
-    x = (x | (x << 3)) & 0x11111111u;
-    return x;
-}
-
-// Counts of chains 8 i .. 8 i + 7 as nibbles (chain 8 i + j at bits 4 j).
-__device__ __forceinline__ uint32_t nibbles(const uint64_t* pl, int i)
-{
-    const int sh = 8 * i;
-    return spread8((uint32_t)(pl[0] >> sh)) | (spread8((uint32_t)(pl[1] >> sh)) << 1) |
-           (spread8((uint32_t)(pl[2] >> sh)) << 2) | (spread8((uint32_t)(pl[3] >> sh)) << 3);
 }
 
 // Count of chain c from np bit planes.
@@ -103,8 +89,13 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
     for (int32_t i = tid; i < n; i += nthr) L.sp[i] = gstate[i];
     const SG_G uint32_t* gthr = gl(up->thr);
     for (int i = tid; i < kVbmChains * kThrSpan; i += nthr) {
-        const int c = i / kThrSpan, x = i - c * kThrSpan - 16;
+        const int c = i / kThrSpan, x = 15 - (i - c * kThrSpan);
         L.thr[i] = x <= 0 ? 0x10000u : (c < nch ? gthr[c * kVbXMax + x] : 0u);
+    }
+    for (int i = tid; i < 256; i += nthr) {
+        unsigned long long v = 0ull;
+        for (int j = 0; j < 8; ++j) v |= (unsigned long long)((i >> j) & 1) << (8 * j);
+        L.spr8[i] = v;
     }
     if (tid < kVbmChains) {
         L.ri[2 * tid] = up->rep[tid];
@@ -119,8 +110,65 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
     const SG_G int32_t* __restrict__ row = gl(up->row);
     const SG_G uint32_t* __restrict__ ent = gl(up->ent);
     const SG_G uint64_t* __restrict__ jw = gl(up->jw);
-    const uint32_t* xw = (const uint32_t*)(L.xch + wave * 64);
-    const char* thb = (const char*)L.thr;
+
+    // Adjacency prefetch over the wavefront's chunk sequence (class by class,
+    // sweep after sweep): the rows of the chunk after next and the first four
+    // entries and coupling words of the next chunk are loaded while a chunk is
+    // updated (the adjacency does not depend on the spins, so the loads run
+    // across class barriers; every entry read stays inside the padded arrays).
+    struct Cur {
+        int32_t s, k, j;
+    };
+    struct Stg {
+        int32_t qb, lo, hi;
+        int32_t r0, d;
+        uint32_t e[4];
+        uint64_t jv[4];
+    };
+    auto cnk = [&](int32_t k) {
+        const int32_t lo = __builtin_amdgcn_readfirstlane(L.cls[k]);
+        const int32_t hi = __builtin_amdgcn_readfirstlane(L.cls[k + 1]);
+        return hi > lo ? ((hi - 1) >> 6) - (lo >> 6) + 1 : 0;
+    };
+    // the next chunk of this wavefront after c; false past the launch
+    auto advance = [&](Cur& c) -> bool {
+        c.j += W;
+        for (;;) {
+            if (c.j < cnk(c.k)) return true;
+            c.j = wave;
+            if (++c.k == ncls) {
+                c.k = 0;
+                if (++c.s == nsw) return false;
+            }
+        }
+    };
+    auto rows = [&](const Cur& c, Stg& g) {
+        g.lo = __builtin_amdgcn_readfirstlane(L.cls[c.k]);
+        g.hi = __builtin_amdgcn_readfirstlane(L.cls[c.k + 1]);
+        g.qb = ((g.lo >> 6) + c.j) << 6;
+        const int32_t q = g.qb + lane;
+        const bool act = q >= g.lo && q < g.hi;
+        g.r0 = act ? row[q] : 0;
+        g.d = act ? row[q + 1] - g.r0 : 0;
+    };
+    auto ents = [&](Stg& g) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            g.e[i] = ent[g.r0 + i];
+            g.jv[i] = jw[g.r0 + i];
+        }
+    };
+    Stg S0, S1, SR;
+    S1.qb = S1.lo = S1.hi = S1.r0 = S1.d = 0;
+    SR.qb = SR.lo = SR.hi = SR.r0 = SR.d = 0;
+    Cur cR = {0, 0, wave - W};
+    bool haveR = nsw > 0 && advance(cR);
+    if (haveR) {
+        rows(cR, S0);
+        ents(S0);
+        haveR = advance(cR);
+        if (haveR) rows(cR, SR);
+    }
 
     for (int32_t s = 0; s < nsw; ++s) {
         const uint32_t t = (uint32_t)(t0 + s);
@@ -130,36 +178,74 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
 #pragma unroll
         for (int k = 0; k < 8; ++k) ap[k] = 0ull;
         for (int32_t k = 0; k < ncls; ++k) {
-            const int32_t lo = __builtin_amdgcn_readfirstlane(L.cls[k]);
-            const int32_t hi = __builtin_amdgcn_readfirstlane(L.cls[k + 1]);
-            const int32_t nck = hi > lo ? ((hi - 1) >> 6) - (lo >> 6) + 1 : 0;
+            const int32_t nck = cnk(k);
             for (int32_t j = wave; j < nck; j += W) {
-                const int32_t qb = ((lo >> 6) + j) << 6;
+                // the next chunk's entries, the rows of the one after it
+                S1.qb = SR.qb;
+                S1.lo = SR.lo;
+                S1.hi = SR.hi;
+                S1.r0 = SR.r0;
+                S1.d = SR.d;
+                ents(S1);
+                if (haveR) {
+                    haveR = advance(cR);
+                    if (haveR) rows(cR, SR);
+                }
+                const int32_t qb = S0.qb;
                 const int32_t q = qb + lane;
-                const bool act = q >= lo && q < hi;
-                const int32_t r0 = act ? row[q] : 0;
-                const int32_t d = act ? row[q + 1] - r0 : 0;
+                const bool act = q >= S0.lo && q < S0.hi;
+                const int32_t r0 = S0.r0;
+                const int32_t d = S0.d;
                 const uint64_t own = act ? L.sp[q] : 0ull;
                 const bool wide = __any(d > 15);
                 uint64_t pl[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
-                for (int32_t e = 0; __any(e < d); ++e) {
-                    if (e < d) {
-                        const uint32_t en = ent[r0 + e] & 0x7fffffffu;
-                        const uint64_t u = L.sp[en] ^ own ^ jw[r0 + e];
-                        // add one bit per chain to the bit-sliced counter
-                        uint64_t cy = u;
+                // add one bit per chain to the bit-sliced counter
+                auto add = [&](uint64_t u) {
+                    uint64_t cy = u;
 #pragma unroll
-                        for (int b = 0; b < 6; ++b) {
-                            if (b >= 4 && !wide) break;
-                            const uint64_t nc = pl[b] & cy;
-                            pl[b] ^= cy;
-                            cy = nc;
-                        }
+                    for (int b = 0; b < 6; ++b) {
+                        if (b >= 4 && !wide) break;
+                        const uint64_t nc = pl[b] & cy;
+                        pl[b] ^= cy;
+                        cy = nc;
                     }
+                };
+                {
+                    uint64_t nb[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) nb[i] = L.sp[S0.e[i] & 0x7fffffffu];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (i < d) add(nb[i] ^ own ^ S0.jv[i]);
                 }
-                // decisions, 8 chains per Philox pass
+                // neighbours past the fourth: four entries at a time
+                for (int32_t e0 = 4; __any(e0 < d); e0 += 4) {
+                    uint32_t en[4];
+                    uint64_t jv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        // (a lane past its degree reads entry 0)
+                        const int32_t ix = e0 + i < d ? r0 + e0 + i : 0;
+                        en[i] = ent[ix] & 0x7fffffffu;
+                        jv[i] = jw[ix];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (e0 + i < d) add(L.sp[en[i]] ^ own ^ jv[i]);
+                }
+                // Decisions, 8 chains per Philox pass.  Below degree 16 the
+                // counts' bit planes are spread to bytes (spr8) and turned into
+                // byte offsets 4 (15 - d) + 8 count = 4 (15 - x) of the chains'
+                // entries in their tables, one bit-field extract per chain; the
+                // sign of e = A - thr decides (shifted into fv, chain 8 i + j at
+                // bit j) and a zero e (a tie) shows in the running minimum.
                 uint64_t A = 0ull, tie = 0ull;
-                const uint32_t tb = (uint32_t)(16 + d) * 4u;   // byte offset of x = d in a chain's table
+                typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+                typedef const __attribute__((address_space(3))) uint16_t lds_u16;
+                const uint32_t thr_off = (uint32_t)(size_t)(const __attribute__((address_space(3))) uint32_t*)L.thr;
+                const uint32_t rh_off = (uint32_t)(size_t)(const __attribute__((address_space(3))) uint4*)(L.xch + wave * 64) +
+                                        (uint32_t)(lane >> 3) * 16u + (uint32_t)(lane & 7) * 2u;
+                const uint32_t bias = __builtin_amdgcn_perm(0u, (uint32_t)(60 - 4 * d), 0u);
                 for (int i = 0; i < 8; ++i) {
                     if (8 * i >= nch) break;
                     {
@@ -170,23 +256,54 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                         L.xch[wave * 64 + lane] = make_uint4(B.x, B.y, B.z, B.w);
                     }
                     wave_sync_m();
-                    const uint32_t nw = wide ? 0u : nibbles(pl, i);
+                    if (!wide) {
+                        uint32_t olo = bias, ohi = bias;   // chains 8 i .. 8 i + 3, 8 i + 4 .. 8 i + 7
 #pragma unroll
-                    for (int c8 = 0; c8 < 8; ++c8) {
-                        const int c = 8 * i + c8;
-                        if (c >= nch) break;
-                        const uint32_t rw = xw[(c8 * 8 + (lane >> 3)) * 4 + ((lane & 7) >> 1)];
-                        const uint32_t rh = (rw >> (16 * (lane & 1))) & 0xffffu;
-                        uint32_t th;
-                        if (!wide) {
-                            const uint32_t u = (nw >> (4 * c8)) & 0xfu;
-                            th = *(const uint32_t*)(thb + (c * kThrSpan * 4) + (tb - 8u * u));
-                        } else {
-                            const int32_t x = d - 2 * count_of(pl, 6, c);
-                            th = x <= 0 ? 0x10000u : gthr[c * kVbXMax + x];
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t by = __builtin_amdgcn_ubfe((uint32_t)(pl[k] >> (32 * (i >> 2))),
+                                                                      8u * (uint32_t)(i & 3), 8u);
+                            const unsigned long long sp = L.spr8[by];
+                            olo += (uint32_t)sp << (3 + k);
+                            ohi += (uint32_t)(sp >> 32) << (3 + k);
                         }
-                        A |= (uint64_t)(rh < th) << c;
-                        tie |= (uint64_t)(rh == th) << c;
+                        uint32_t fv = 0u, emin = 0xFFFFFFFFu;
+#pragma unroll
+                        for (int c8 = 7; c8 >= 0; --c8) {
+                            const int c = 8 * i + c8;
+                            if (c < nch) {
+                                const uint32_t off = __builtin_amdgcn_ubfe(c8 < 4 ? olo : ohi, 8u * (uint32_t)(c8 & 3), 8u);
+                                const uint32_t th = *(lds_u32*)(size_t)(thr_off + (uint32_t)(c * kThrSpan * 4) + off);
+                                const uint32_t rh = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
+                                const uint32_t e = rh - th;
+                                fv = __builtin_amdgcn_alignbit(fv, e, 31u);
+                                emin = min(emin, e);
+                            } else {
+                                fv <<= 1;
+                            }
+                        }
+                        A |= (uint64_t)(fv & 0xffu) << (8 * i);
+                        if (__builtin_amdgcn_ballot_w64(act && emin == 0u) != 0ull) {
+                            // a half-word equals a threshold (rare): mark those chains
+                            for (int c8 = 0; c8 < 8; ++c8) {
+                                const int c = 8 * i + c8;
+                                if (c >= nch) break;
+                                const uint32_t off = __builtin_amdgcn_ubfe(c8 < 4 ? olo : ohi, 8u * (uint32_t)(c8 & 3), 8u);
+                                const uint32_t th = *(lds_u32*)(size_t)(thr_off + (uint32_t)(c * kThrSpan * 4) + off);
+                                const uint32_t rh = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
+                                tie |= (uint64_t)(rh == th) << c;
+                            }
+                        }
+                    } else {
+                        // a degree above 15 in the chunk: 6 planes, thresholds from HBM
+                        for (int c8 = 0; c8 < 8; ++c8) {
+                            const int c = 8 * i + c8;
+                            if (c >= nch) break;
+                            const uint32_t rh = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
+                            const int32_t x = d - 2 * count_of(pl, 6, c);
+                            const uint32_t th = x <= 0 ? 0x10000u : gthr[c * kVbXMax + x];
+                            A |= (uint64_t)(rh < th) << c;
+                            tie |= (uint64_t)(rh == th) << c;
+                        }
                     }
                     wave_sync_m();
                 }
@@ -215,6 +332,7 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                     ap[b] ^= cy;
                     cy = nc;
                 }
+                S0 = S1;
             }
             __syncthreads();
         }
@@ -346,7 +464,8 @@ size_t vbm_lds_bytes(int32_t n, int threads)
 {
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
     return r16((size_t)n * 8) + r16((size_t)kVbmChains * kThrSpan * 4) + r16((size_t)kVbmChains * 8) +
-           r16((size_t)(kMaxClsM + 4) * 4) + r16((size_t)kVbmChains * 8) + (size_t)(threads / 64) * 64 * 16;
+           r16((size_t)(kMaxClsM + 4) * 4) + r16((size_t)kVbmChains * 8) + (size_t)(threads / 64) * 64 * 16 +
+           256 * 8;
 }
 
 hipError_t vbm_init(const VbmUnit* units, int n_units, hipStream_t s)
