@@ -246,6 +246,9 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                 const uint32_t rh_off = (uint32_t)(size_t)(const __attribute__((address_space(3))) uint4*)(L.xch + wave * 64) +
                                         (uint32_t)(lane >> 3) * 16u + (uint32_t)(lane & 7) * 2u;
                 const uint32_t bias = __builtin_amdgcn_perm(0u, (uint32_t)(60 - 4 * d), 0u);
+                // (passes unrolled: constant shifts; the chains of a pass are
+                // decided without branches, those past nch masked off)
+#pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     if (8 * i >= nch) break;
                     {
@@ -256,6 +259,7 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                         L.xch[wave * 64 + lane] = make_uint4(B.x, B.y, B.z, B.w);
                     }
                     wave_sync_m();
+                    const uint32_t live = nch - 8 * i >= 8 ? 0xffu : (1u << (nch - 8 * i)) - 1u;
                     if (!wide) {
                         uint32_t olo = bias, ohi = bias;   // chains 8 i .. 8 i + 3, 8 i + 4 .. 8 i + 7
 #pragma unroll
@@ -266,43 +270,39 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                             olo += (uint32_t)sp << (3 + k);
                             ohi += (uint32_t)(sp >> 32) << (3 + k);
                         }
+                        uint32_t th[8], rh[8];
+#pragma unroll
+                        for (int c8 = 0; c8 < 8; ++c8) {
+                            const uint32_t cb = (uint32_t)min(8 * i + c8, nch - 1) * (uint32_t)(kThrSpan * 4);
+                            const uint32_t off = __builtin_amdgcn_ubfe(c8 < 4 ? olo : ohi, 8u * (uint32_t)(c8 & 3), 8u);
+                            th[c8] = *(lds_u32*)(size_t)(thr_off + cb + off);
+                            rh[c8] = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
+                        }
                         uint32_t fv = 0u, emin = 0xFFFFFFFFu;
 #pragma unroll
                         for (int c8 = 7; c8 >= 0; --c8) {
-                            const int c = 8 * i + c8;
-                            if (c < nch) {
-                                const uint32_t off = __builtin_amdgcn_ubfe(c8 < 4 ? olo : ohi, 8u * (uint32_t)(c8 & 3), 8u);
-                                const uint32_t th = *(lds_u32*)(size_t)(thr_off + (uint32_t)(c * kThrSpan * 4) + off);
-                                const uint32_t rh = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
-                                const uint32_t e = rh - th;
-                                fv = __builtin_amdgcn_alignbit(fv, e, 31u);
-                                emin = min(emin, e);
-                            } else {
-                                fv <<= 1;
-                            }
+                            const uint32_t e = rh[c8] - th[c8];
+                            fv = __builtin_amdgcn_alignbit(fv, e, 31u);
+                            emin = min(emin, e);
                         }
-                        A |= (uint64_t)(fv & 0xffu) << (8 * i);
+                        A |= (uint64_t)(fv & live) << (8 * i);
                         if (__builtin_amdgcn_ballot_w64(act && emin == 0u) != 0ull) {
                             // a half-word equals a threshold (rare): mark those chains
-                            for (int c8 = 0; c8 < 8; ++c8) {
-                                const int c = 8 * i + c8;
-                                if (c >= nch) break;
-                                const uint32_t off = __builtin_amdgcn_ubfe(c8 < 4 ? olo : ohi, 8u * (uint32_t)(c8 & 3), 8u);
-                                const uint32_t th = *(lds_u32*)(size_t)(thr_off + (uint32_t)(c * kThrSpan * 4) + off);
-                                const uint32_t rh = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
-                                tie |= (uint64_t)(rh == th) << c;
-                            }
+                            uint32_t tm = 0u;
+#pragma unroll
+                            for (int c8 = 0; c8 < 8; ++c8) tm |= (uint32_t)(rh[c8] == th[c8]) << c8;
+                            tie |= (uint64_t)(tm & live) << (8 * i);
                         }
                     } else {
                         // a degree above 15 in the chunk: 6 planes, thresholds from HBM
                         for (int c8 = 0; c8 < 8; ++c8) {
                             const int c = 8 * i + c8;
                             if (c >= nch) break;
-                            const uint32_t rh = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
+                            const uint32_t rh1 = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
                             const int32_t x = d - 2 * count_of(pl, 6, c);
-                            const uint32_t th = x <= 0 ? 0x10000u : gthr[c * kVbXMax + x];
-                            A |= (uint64_t)(rh < th) << c;
-                            tie |= (uint64_t)(rh == th) << c;
+                            const uint32_t th1 = x <= 0 ? 0x10000u : gthr[c * kVbXMax + x];
+                            A |= (uint64_t)(rh1 < th1) << c;
+                            tie |= (uint64_t)(rh1 == th1) << c;
                         }
                     }
                     wave_sync_m();
