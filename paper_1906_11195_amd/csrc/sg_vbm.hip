@@ -261,21 +261,26 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                     wave_sync_m();
                     const uint32_t live = nch - 8 * i >= 8 ? 0xffu : (1u << (nch - 8 * i)) - 1u;
                     if (!wide) {
+                        // (the four spread words are read before any is used,
+                        // so that their LDS round trips overlap)
+                        unsigned long long sp[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            sp[k] = L.spr8[__builtin_amdgcn_ubfe((uint32_t)(pl[k] >> (32 * (i >> 2))),
+                                                                 8u * (uint32_t)(i & 3), 8u)];
                         uint32_t olo = bias, ohi = bias;   // chains 8 i .. 8 i + 3, 8 i + 4 .. 8 i + 7
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            const uint32_t by = __builtin_amdgcn_ubfe((uint32_t)(pl[k] >> (32 * (i >> 2))),
-                                                                      8u * (uint32_t)(i & 3), 8u);
-                            const unsigned long long sp = L.spr8[by];
-                            olo += (uint32_t)sp << (3 + k);
-                            ohi += (uint32_t)(sp >> 32) << (3 + k);
+                            olo += (uint32_t)sp[k] << (3 + k);
+                            ohi += (uint32_t)(sp[k] >> 32) << (3 + k);
                         }
+                        // chain c's table at the constant offset c kThrSpan 4 (a chain
+                        // past the unit's count reads zeros, masked off below)
                         uint32_t th[8], rh[8];
 #pragma unroll
                         for (int c8 = 0; c8 < 8; ++c8) {
-                            const uint32_t cb = (uint32_t)min(8 * i + c8, nch - 1) * (uint32_t)(kThrSpan * 4);
                             const uint32_t off = __builtin_amdgcn_ubfe(c8 < 4 ? olo : ohi, 8u * (uint32_t)(c8 & 3), 8u);
-                            th[c8] = *(lds_u32*)(size_t)(thr_off + cb + off);
+                            th[c8] = *(lds_u32*)(size_t)(thr_off + (uint32_t)((8 * i + c8) * kThrSpan * 4) + off);
                             rh[c8] = *(lds_u16*)(size_t)(rh_off + (uint32_t)(c8 * 128));
                         }
                         uint32_t fv = 0u, emin = 0xFFFFFFFFu;
