@@ -198,41 +198,6 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                 const int32_t d = S0.d;
                 const uint64_t own = act ? L.sp[q] : 0ull;
                 const bool wide = __any(d > 15);
-                uint64_t pl[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
-                // add one bit per chain to the bit-sliced counter
-                auto add = [&](uint64_t u) {
-                    uint64_t cy = u;
-#pragma unroll
-                    for (int b = 0; b < 6; ++b) {
-                        if (b >= 4 && !wide) break;
-                        const uint64_t nc = pl[b] & cy;
-                        pl[b] ^= cy;
-                        cy = nc;
-                    }
-                };
-                {
-                    uint64_t nb[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) nb[i] = L.sp[S0.e[i] & 0x7fffffffu];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (i < d) add(nb[i] ^ own ^ S0.jv[i]);
-                }
-                // neighbours past the fourth: four entries at a time
-                for (int32_t e0 = 4; __any(e0 < d); e0 += 4) {
-                    uint32_t en[4];
-                    uint64_t jv[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        // (a lane past its degree reads entry 0)
-                        const int32_t ix = e0 + i < d ? r0 + e0 + i : 0;
-                        en[i] = ent[ix] & 0x7fffffffu;
-                        jv[i] = jw[ix];
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (e0 + i < d) add(L.sp[en[i]] ^ own ^ jv[i]);
-                }
                 // Decisions, 8 chains per Philox pass.  Below degree 16 the
                 // counts' bit planes are spread to bytes (spr8) and turned into
                 // byte offsets 4 (15 - d) + 8 count = 4 (15 - x) of the chains'
@@ -245,22 +210,88 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                 const uint32_t thr_off = (uint32_t)(size_t)(const __attribute__((address_space(3))) uint32_t*)L.thr;
                 const uint32_t rh_off = (uint32_t)(size_t)(const __attribute__((address_space(3))) uint4*)(L.xch + wave * 64) +
                                         (uint32_t)(lane >> 3) * 16u + (uint32_t)(lane & 7) * 2u;
-                const uint32_t bias = __builtin_amdgcn_perm(0u, (uint32_t)(60 - 4 * d), 0u);
-                // (passes unrolled: constant shifts; the chains of a pass are
-                // decided without branches, those past nch masked off)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    if (8 * i >= nch) break;
-                    {
-                        const int cc = 8 * i + (lane >> 3);
-                        const int ce = cc < nch ? cc : 0;
-                        const U4 B = philox_stream(key, ((uint32_t)qb >> 3) + (uint32_t)(lane & 7), t, kDomSweepHi,
-                                                   L.ri[2 * ce], L.ri[2 * ce + 1]);
-                        L.xch[wave * 64 + lane] = make_uint4(B.x, B.y, B.z, B.w);
-                    }
+                // pass i's Philox blocks: lane l draws chain 8 i + l / 8 for the
+                // 8 positions of group l mod 8
+                auto draw = [&](int i) {
+                    const int cc = 8 * i + (lane >> 3);
+                    const int ce = cc < nch ? cc : 0;
+                    const U4 B = philox_stream(key, ((uint32_t)qb >> 3) + (uint32_t)(lane & 7), t, kDomSweepHi,
+                                               L.ri[2 * ce], L.ri[2 * ce + 1]);
+                    L.xch[wave * 64 + lane] = make_uint4(B.x, B.y, B.z, B.w);
                     wave_sync_m();
-                    const uint32_t live = nch - 8 * i >= 8 ? 0xffu : (1u << (nch - 8 * i)) - 1u;
-                    if (!wide) {
+                };
+                // ties: A equals the high half of the threshold; decided on
+                // the low halves (second stream), rare
+                auto resolve = [&](const uint64_t* planes, int np) {
+                    if (!act) {
+                        A = 0ull;
+                        tie = 0ull;
+                    }
+                    if (__any(tie != 0ull)) {
+                        uint64_t tm = tie;
+                        while (tm) {
+                            const int c = __builtin_ctzll(tm);
+                            tm &= tm - 1ull;
+                            const int32_t x = d - 2 * count_of(planes, np, c);
+                            const U4 Bl = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, L.ri[2 * c], L.ri[2 * c + 1]);
+                            if (half_word(Bl, (uint32_t)q & 7u) < gthr[kVbmChains * kVbXMax + c * kVbXMax + x]) A |= 1ull << c;
+                        }
+                    }
+                };
+                if (!wide) {
+                    // counts below 16: four planes.  The first four neighbours are
+                    // added one by one into only the planes their running count can
+                    // reach, further ones four entries at a time
+                    uint64_t pl[4];
+                    {
+                        uint64_t nb[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) nb[i] = L.sp[S0.e[i] & 0x7fffffffu];
+                        const uint64_t u0 = d > 0 ? nb[0] ^ own ^ S0.jv[0] : 0ull;
+                        const uint64_t u1 = d > 1 ? nb[1] ^ own ^ S0.jv[1] : 0ull;
+                        pl[0] = u0 ^ u1;
+                        pl[1] = u0 & u1;
+                        const uint64_t u2 = d > 2 ? nb[2] ^ own ^ S0.jv[2] : 0ull;
+                        uint64_t c0 = pl[0] & u2;
+                        pl[0] ^= u2;
+                        pl[2] = pl[1] & c0;
+                        pl[1] ^= c0;
+                        const uint64_t u3 = d > 3 ? nb[3] ^ own ^ S0.jv[3] : 0ull;
+                        c0 = pl[0] & u3;
+                        pl[0] ^= u3;
+                        pl[2] |= pl[1] & c0;
+                        pl[1] ^= c0;
+                        pl[3] = 0ull;
+                    }
+                    for (int32_t e0 = 4; __any(e0 < d); e0 += 4) {
+                        uint32_t en[4];
+                        uint64_t jv[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            // (a lane past its degree reads entry 0)
+                            const int32_t ix = e0 + i < d ? r0 + e0 + i : 0;
+                            en[i] = ent[ix] & 0x7fffffffu;
+                            jv[i] = jw[ix];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            uint64_t cy = e0 + i < d ? L.sp[en[i]] ^ own ^ jv[i] : 0ull;
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) {
+                                const uint64_t nc = pl[b] & cy;
+                                pl[b] ^= cy;
+                                cy = nc;
+                            }
+                        }
+                    }
+                    const uint32_t bias = __builtin_amdgcn_perm(0u, (uint32_t)(60 - 4 * d), 0u);
+                    // (passes unrolled: constant shifts; the chains of a pass are
+                    // decided without branches, those past nch masked off)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        if (8 * i >= nch) break;
+                        draw(i);
+                        const uint32_t live = nch - 8 * i >= 8 ? 0xffu : (1u << (nch - 8 * i)) - 1u;
                         // (the four spread words are read before any is used,
                         // so that their LDS round trips overlap)
                         unsigned long long sp[4];
@@ -298,8 +329,35 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                             for (int c8 = 0; c8 < 8; ++c8) tm |= (uint32_t)(rh[c8] == th[c8]) << c8;
                             tie |= (uint64_t)(tm & live) << (8 * i);
                         }
-                    } else {
-                        // a degree above 15 in the chunk: 6 planes, thresholds from HBM
+                        wave_sync_m();
+                    }
+                    resolve(pl, 4);
+                } else {
+                    // a degree above 15 in the chunk: six planes, thresholds from HBM
+                    uint64_t pl[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+                    for (int32_t e0 = 0; __any(e0 < d); e0 += 4) {
+                        uint32_t en[4];
+                        uint64_t jv[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int32_t ix = e0 + i < d ? r0 + e0 + i : 0;
+                            en[i] = ent[ix] & 0x7fffffffu;
+                            jv[i] = jw[ix];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            uint64_t cy = e0 + i < d ? L.sp[en[i]] ^ own ^ jv[i] : 0ull;
+#pragma unroll
+                            for (int b = 0; b < 6; ++b) {
+                                const uint64_t nc = pl[b] & cy;
+                                pl[b] ^= cy;
+                                cy = nc;
+                            }
+                        }
+                    }
+                    for (int i = 0; i < 8; ++i) {
+                        if (8 * i >= nch) break;
+                        draw(i);
                         for (int c8 = 0; c8 < 8; ++c8) {
                             const int c = 8 * i + c8;
                             if (c >= nch) break;
@@ -309,24 +367,9 @@ __global__ void __launch_bounds__(1024) vbm_sweep_kernel(const VbmUnit* __restri
                             A |= (uint64_t)(rh1 < th1) << c;
                             tie |= (uint64_t)(rh1 == th1) << c;
                         }
+                        wave_sync_m();
                     }
-                    wave_sync_m();
-                }
-                if (!act) {
-                    A = 0ull;
-                    tie = 0ull;
-                }
-                if (__any(tie != 0ull)) {
-                    // A equals the high half of the threshold: decide on the
-                    // low halves (second stream)
-                    uint64_t tm = tie;
-                    while (tm) {
-                        const int c = __builtin_ctzll(tm);
-                        tm &= tm - 1ull;
-                        const int32_t x = d - 2 * count_of(pl, wide ? 6 : 4, c);
-                        const U4 Bl = philox_stream(key, (uint32_t)q >> 3, t, kDomSweepLo, L.ri[2 * c], L.ri[2 * c + 1]);
-                        if (half_word(Bl, (uint32_t)q & 7u) < gthr[kVbmChains * kVbXMax + c * kVbXMax + x]) A |= 1ull << c;
-                    }
+                    resolve(pl, 6);
                 }
                 if (act) L.sp[q] = own ^ A;
                 // count the accepted flips in the bit-sliced counter
