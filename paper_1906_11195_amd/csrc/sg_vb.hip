@@ -607,6 +607,8 @@ __device__ __forceinline__ void win_fold(uint32_t* cnt, uint32_t ones, uint32_t 
     for (int c = 0; c < RPAD; ++c) cnt[c] = 4u * cnt[c] + c1[c] + 2u * c2[c];
 }
 
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v);
+
 // Windowed correlation (the paper's estimator: C(t_w + t, t_w) averaged over
 // minor-third intervals of t_w + t, ratio 2^(1/4); Results and discussion,
 // and the SI section on the extrapolation to large sizes and times), at the
@@ -618,12 +620,16 @@ __device__ __forceinline__ void win_fold(uint32_t* cnt, uint32_t ones, uint32_t 
 // 16-byte groups; the words past state_words are zero on both sides), so the
 // XOR of two words holds every chain's disagreements; a thread adds them up
 // bit-sliced (carry-save adders) and counts the chains' fields of the carry
-// planes.  The
-// stored words are streamed from HBM with 16-byte loads, four groups of two
-// waiting times in flight per lane.  Each thread counts (and, at the waiting
-// times, stores) the groups i = tid + member * threads (mod members *
-// threads): the members of a split unit count disjoint words and no thread
-// reads another's stores.
+// planes.  The work is cut into blocks of 64 groups of one waiting time's
+// row, taken in (waiting time, block) order as contiguous ranges by the
+// wavefronts of all members (lane l counts group 64 b + l of block b): a
+// lane keeps adding into the same carry-save planes until its wavefront
+// reaches the next waiting time, so the planes are folded and the wavefront
+// sums formed once or twice per sweep instead of once per waiting time.  The
+// stored words are streamed from HBM with 16-byte loads, four blocks in
+// flight per lane.  At the waiting times each thread stores the groups
+// i = tid + member * threads (mod members * threads); no thread reads another's
+// stores.
 template <int RPAD>
 __device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ up, uint32_t sp_off,
                                                    uint32_t acc_off, int64_t tau, int32_t k_store)
@@ -633,7 +639,7 @@ __device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ u
     typedef __attribute__((address_space(3))) uint32_t lds_u32;
     const lds_u4* sp4 = (const lds_u4*)(size_t)sp_off;
     lds_u32* wacc = (lds_u32*)(size_t)acc_off;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
     const int32_t nch = up->nch;
     const int32_t sw4 = (up->state_words + 3) >> 2;
     // waiting times before tau: t_w = 0, and t_w = 2^(k-1) < tau for k >= 1
@@ -643,52 +649,56 @@ __device__ __attribute__((noinline)) void vb_window(const VbUnit* __restrict__ u
     SG_G v4u* ws4 = (SG_G v4u*)gl(up->wsnap);
     for (int i = tid; i < kv * RPAD; i += nthr) wacc[i] = 0u;
     __syncthreads();
+    const int32_t nbr = (sw4 + 63) >> 6;   // blocks per row
+    const int32_t nb = kv * nbr;
+    const int32_t W = nthr >> 6;
+    const int32_t gw = __builtin_amdgcn_readfirstlane(up->member * W + (tid >> 6));
+    const int32_t GW = up->members * W;
+    const int32_t per = (nb + GW - 1) / GW;
+    const int32_t b0 = min(gw * per, nb), b1 = min(b0 + per, nb);
     const v4u zero = {0u, 0u, 0u, 0u};
-    for (int32_t k = 0; k < kv; k += 2) {
-        const bool two = k + 1 < kv;
-        const SG_G v4u* r0 = ws4 + (int64_t)k * sw4;
-        const SG_G v4u* r1 = ws4 + (int64_t)(two ? k + 1 : k) * sw4;
-        uint32_t c0[RPAD], c1[RPAD];
+    uint32_t cnt[RPAD];
 #pragma unroll
-        for (int c = 0; c < RPAD; ++c) {
-            c0[c] = 0u;
-            c1[c] = 0u;
-        }
-        uint32_t on0 = 0u, tw0 = 0u, on1 = 0u, tw1 = 0u;   // bit-sliced counters
-        for (int32_t i0 = w0; i0 < sw4; i0 += U * stride) {
-            v4u a[U], b0[U], b1[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t i = i0 + u * stride;
-                const bool ok = i < sw4;
-                b0[u] = ok ? r0[i] : zero;
-                b1[u] = ok && two ? r1[i] : zero;
-                a[u] = ok ? sp4[i] : zero;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                win_add4<RPAD>(on0, tw0, c0, a[u], b0[u], nch);
-                if (two) win_add4<RPAD>(on1, tw1, c1, a[u], b1[u], nch);
-            }
-        }
-        win_fold<RPAD>(c0, on0, tw0, nch);
-        win_fold<RPAD>(c1, on1, tw1, nch);
+    for (int c = 0; c < RPAD; ++c) cnt[c] = 0u;
+    uint32_t ones = 0u, twos = 0u;   // bit-sliced counters
+    int32_t kc = b0 / nbr;           // the waiting time being counted
+    auto flush = [&](int32_t k) {
+        win_fold<RPAD>(cnt, ones, twos, nch);
 #pragma unroll
         for (int c = 0; c < RPAD; ++c) {
             if (c < nch) {
-                uint32_t v0 = c0[c], v1 = c1[c];
+                const uint32_t v = wave_sum(cnt[c]);
+                if (lane == 0 && v) atomicAdd((uint32_t*)&wacc[k * RPAD + c], v);
+            }
+            cnt[c] = 0u;
+        }
+        ones = twos = 0u;
+    };
+    for (int32_t b = b0; b < b1; b += U) {
+        v4u a[U], w[U];
+        int32_t kb[U];
 #pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) {
-                    v0 += (uint32_t)__shfl_xor((int)v0, o);
-                    v1 += (uint32_t)__shfl_xor((int)v1, o);
+        for (int u = 0; u < U; ++u) {
+            const int32_t bb = b + u;
+            const int32_t k = bb < b1 ? bb / nbr : kc;
+            const int32_t g = (bb - k * nbr) * 64 + lane;
+            const bool ok = bb < b1 && g < sw4;
+            kb[u] = k;
+            w[u] = ok ? ws4[(int64_t)k * sw4 + g] : zero;
+            a[u] = ok ? sp4[g] : zero;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b + u < b1) {
+                if (kb[u] != kc) {
+                    flush(kc);
+                    kc = kb[u];
                 }
-                if ((tid & 63) == 0) {
-                    if (v0) atomicAdd((uint32_t*)&wacc[k * RPAD + c], v0);
-                    if (two && v1) atomicAdd((uint32_t*)&wacc[(k + 1) * RPAD + c], v1);
-                }
+                win_add4<RPAD>(ones, twos, cnt, a[u], w[u], nch);
             }
         }
     }
+    if (b1 > b0) flush(kc);
     if (k_store >= 0) {
         SG_G v4u* dst = ws4 + (int64_t)k_store * sw4;
         for (int32_t i = w0; i < sw4; i += stride) dst[i] = sp4[i];
