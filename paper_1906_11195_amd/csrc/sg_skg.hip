@@ -259,12 +259,17 @@ __global__ void __launch_bounds__(64) skg_recompute_kernel(const SkSample* __res
 // Bond sums B = (1/2) sum_i s_i (J s)_i of every snapshot (chain c, grid time
 // k) of one sample, in double and in a fixed order: each wavefront forms
 // partial sums over 16 rows, written to part[sample][row block][column], then
-// skg_bond_reduce adds the row blocks in order.  grid = (row blocks of 16,
+// skg_bond_reduce adds the row blocks in order.  The columns (snapshots) go in
+// tiles of 8, so a row of J is read once per tile: lane l adds, for its
+// entries j = l, l + 64, ..., the signed couplings s_j J_ij of each column,
+// multiplies by the row's spin s_i (the same on every lane) and keeps the
+// sum; the wavefront sum is formed once per tile.  grid = (row blocks of 16,
 // samples).
 __global__ void __launch_bounds__(64) skg_bond_kernel(const SkSample* __restrict__ samples,
                                                       const SkChain* __restrict__ chains, int kd, int nrb,
                                                       int ncol_cap, double* __restrict__ part)
 {
+    constexpr int CT = 8;   // columns per tile
     const SkSample* sm = samples + blockIdx.y;
     const int32_t n = sm->n;
     const int lane = threadIdx.x;
@@ -272,23 +277,38 @@ __global__ void __launch_bounds__(64) skg_bond_kernel(const SkSample* __restrict
     if (i0 >= n) return;
     const SG_G float* __restrict__ J = gl(sm->Jf);
     const int32_t ncol = sm->nch * kd;
-    for (int32_t col = 0; col < ncol; ++col) {
-        const SkChain* ch = chains + sm->chain0 + col / kd;
-        const int32_t k = col % kd;
-        const SG_G uint32_t* sn = gl(ch->snap) + (int64_t)k * ch->words_n;
-        double acc = 0.0;
-        for (int32_t i = i0; i < min(n, i0 + 16); ++i) {
+    const int32_t i1 = min(n, i0 + 16);
+    for (int32_t c0 = 0; c0 < ncol; c0 += CT) {
+        const SG_G uint32_t* sn[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int32_t col = min(c0 + c, ncol - 1);
+            const SkChain* ch = chains + sm->chain0 + col / kd;
+            sn[c] = gl(ch->snap) + (int64_t)(col % kd) * ch->words_n;
+        }
+        double acc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[c] = 0.0;
+        for (int32_t i = i0; i < i1; ++i) {
             const SG_G float* row = J + (int64_t)i * n;
-            double d = 0.0;
+            double d[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) d[c] = 0.0;
             for (int32_t j = lane; j < n; j += 64) {
                 const double v = (double)row[j];
-                d += ((sn[j >> 5] >> (j & 31)) & 1u) ? -v : v;
+#pragma unroll
+                for (int c = 0; c < CT; ++c) d[c] += ((sn[c][j >> 5] >> (j & 31)) & 1u) ? -v : v;
             }
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o);
-            acc += ((sn[i >> 5] >> (i & 31)) & 1u) ? -d : d;
+            for (int c = 0; c < CT; ++c) acc[c] += ((sn[c][i >> 5] >> (i & 31)) & 1u) ? -d[c] : d[c];
         }
-        if (lane == 0) part[((int64_t)blockIdx.y * nrb + blockIdx.x) * ncol_cap + col] = acc;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            double a = acc[c];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+            if (lane == 0 && c0 + c < ncol) part[((int64_t)blockIdx.y * nrb + blockIdx.x) * ncol_cap + c0 + c] = a;
+        }
     }
 }
 
