@@ -91,28 +91,60 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
     const bool vec4 = (n & 3) == 0;   // rows start 16-byte aligned
     unsigned long long acc = 0;   // accepted flips (wave 0, lane 0)
 
+    // 1. the coupling tile of a block, T[i][j] = J[p0 + i][p0 + j], is loaded
+    //    into registers (16 floats per thread, 16-byte loads when the rows
+    //    are 16-byte aligned) while the block before it is decided and
+    //    applied, and stored to LDS when its turn comes
+    static_assert(kSkgThreads == 256, "a thread holds 16 floats of a 64 x 64 tile");
+    v4f tv[4];
+    float ts[16];
+    auto tile_load = [&](int32_t bb) {
+        const int32_t q0 = bb << 6;
+        const int32_t mm = min(64, n - q0);
+        if (vec4) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int32_t idx = tid + k * kSkgThreads;
+                const int32_t i = idx >> 4, j = (idx & 15) << 2;
+                const v4f z = {0.f, 0.f, 0.f, 0.f};
+                tv[k] = (i < mm && j < mm) ? *(const SG_G v4f*)(J + (int64_t)(q0 + i) * n + q0 + j) : z;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int32_t idx = tid + k * kSkgThreads;
+                const int32_t i = idx >> 6, j = idx & 63;
+                ts[k] = (i < mm && j < mm) ? J[(int64_t)(q0 + i) * n + q0 + j] : 0.0f;
+            }
+        }
+    };
+    auto tile_store = [&]() {
+        if (vec4) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int32_t idx = tid + k * kSkgThreads;
+                *(v4f*)(L.tile + ((idx >> 4) << 6) + ((idx & 15) << 2)) = tv[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) L.tile[tid + k * kSkgThreads] = ts[k];
+        }
+    };
+    if (nsw > 0) tile_load(0);
+
     for (int32_t s = 0; s < nsw; ++s) {
         const uint32_t t = (uint32_t)(t0 + s);
         for (int32_t b = 0; b < NB; ++b) {
             const int32_t p0 = b << 6;
             const int32_t m = min(64, n - p0);
-            // 1. the block's coupling tile: T[i][j] = J[p0 + i][p0 + j]
-            //    (16-byte loads when the rows are 16-byte aligned)
-            if (vec4) {
-#pragma unroll 4
-                for (int32_t idx = tid; idx < 64 * 16; idx += nthr) {
-                    const int32_t i = idx >> 4, j = (idx & 15) << 2;
-                    v4f v = {0.f, 0.f, 0.f, 0.f};
-                    if (i < m && j < m) v = *(const SG_G v4f*)(J + (int64_t)(p0 + i) * n + p0 + j);
-                    *(v4f*)(L.tile + (i << 6) + j) = v;   // m is a multiple of 4 here
-                }
-            } else {
-                for (int32_t idx = tid; idx < 64 * 64; idx += nthr) {
-                    const int32_t i = idx >> 6, j = idx & 63;
-                    L.tile[idx] = (i < m && j < m) ? J[(int64_t)(p0 + i) * n + p0 + j] : 0.0f;
-                }
-            }
+            tile_store();
             __syncthreads();
+            // the next block's tile (the first block of the next sweep after
+            // the last one)
+            if (b + 1 < NB)
+                tile_load(b + 1);
+            else if (s + 1 < nsw)
+                tile_load(0);
             // 2. decisions (wavefront 0)
             if (wave == 0) {
                 const bool act = lane < m;
