@@ -7,7 +7,8 @@ t1 (bond sums, overlaps, Gram entries, also against the start snapshot when
 t1 is itself a grid time).  The random streams are counter-based and keyed
 by the sweep index (Methods), so nothing but the spins and the time has to be
 carried over.  The uninterrupted run is itself compared with the oracle.
-Per-chain VB (t1 a grid time or not), multispin VB, binary SK (t1 off the
+Per-chain VB (t1 a grid time or not; graph replay, autotuned launch groups,
+units split over two workgroups), multispin VB, binary SK (t1 off the
 recompute period) and real-coupling SK (t1 on it; off it is refused)."""
 import dataclasses
 
@@ -118,3 +119,17 @@ def test_sk_real_couplings_resume():
     with pytest.raises(sg.SgError) as e:
         sg.sg_create_sk(descs, t_max=128, t_start=20)
     assert e.value.code == sg.SG_EINVAL
+
+
+@pytest.mark.parametrize("opts", [dict(graph=True), dict(autotune=True), dict(split_members=2)],
+                         ids=["graph", "autotune", "split"])
+def test_vb_resume_launch_paths(opts):
+    # the resumed context's device sweep counter starts at t_start on every
+    # launch path: captured graph replays, autotuned launch groups (their
+    # trial launches restore the state), units split over two workgroups
+    require_gpu()
+    descs = [sg.VbDesc(n=20000, T=T, seed=13, instance_id=i, graph_id=4, n_replicas=2)
+             for i, T in enumerate((0.7, 1.3))]
+    whole = split_equals_whole("vb", descs, 128, 150, 512, **opts)
+    for i, d in enumerate(descs):
+        assert_instance_equal(whole, i, oracle_vb(d, 278, 512), label="whole run, instance %d" % i)
