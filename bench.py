@@ -588,21 +588,50 @@ def run_cpu_baseline(args, workloads):
                        "one instance per thread (%d host CPUs visible); %.1f s" % (threads, sweeps, cores, el))
 
 
-# The serving legs keep a pool of SERVE_STREAMS streams, one per hardware
-# queue (streams sharing a queue run in submission order, so a batch would
-# wait for every batch enqueued before it on its queue): the process gets at
-# least that many hardware queues, set before HIP starts.
-SERVE_STREAMS = 8
+# The serving legs keep a pool of SERVE_STREAMS streams.  Streams sharing a
+# hardware queue run in submission order, so a batch would wait for every
+# batch enqueued before it on its queue, and so would the measurement of a
+# finished one; the library's own streams and the legacy stream take queues
+# too.  So the serving legs run in a child process with SERVE_QUEUES hardware
+# queues, twice the pool (16 streams on 16 queues: 1.3 s of the mean latency
+# at configured lengths waited on shared queues; on 32: 3 ms), while the
+# other legs keep MAIN_QUEUES (the uneven batch's launch groups on forked
+# streams: 304-306 updates/ns on 8 queues, 287 on 32).  The number is set
+# before HIP starts.
+SERVE_STREAMS = 16
+SERVE_QUEUES = 32
+MAIN_QUEUES = 8
+
+
+def run_serving_child(args, legs):
+    """Runs the serving legs `legs` in a child process of this script with
+    SERVE_QUEUES hardware queues; returns its (serving, serving_full) dicts."""
+    import subprocess
+    import torch
+    torch.cuda.empty_cache()   # this process's cached blocks, for the child's use
+    env = dict(os.environ, GPU_MAX_HW_QUEUES=str(SERVE_QUEUES))
+    cmd = [sys.executable, os.path.abspath(__file__), "--serve-child", "--skip-headline", "--no-cpu-baseline",
+           "--legs", ",".join(legs), "--serve-requests", str(args.serve_requests),
+           "--serve-full-requests", str(args.serve_full_requests), "--serve-max-wall", str(args.serve_max_wall)]
+    out = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, text=True)
+    if out.returncode != 0:
+        raise RuntimeError("serving legs failed in the child process (exit %d)" % out.returncode)
+    d = json.loads(out.stdout.strip().splitlines()[-1])["legs"]
+    return d.get("serving"), d.get("serving_full")
 
 
 def main():
+    child = "--serve-child" in sys.argv
     try:
         hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
     except ValueError:
         hwq = 4
-    if hwq < SERVE_STREAMS:
-        os.environ["GPU_MAX_HW_QUEUES"] = str(SERVE_STREAMS)
+    want = SERVE_QUEUES if child else MAIN_QUEUES
+    if hwq < want:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(want)
     ap = argparse.ArgumentParser()
+    ap.add_argument("--serve-child", action="store_true",
+                    help="internal: run the chosen serving legs in this process (the parent's child)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -685,13 +714,17 @@ def main():
     if "window" in legs:
         window = run_window(args, torch, sg, workloads)
         log("VB windowed C: %.1f updates/ns" % window["updates_per_ns"])
-    if "serving" in legs:
-        serve = run_serving(args, torch, sg, workloads)
-        log("serving: p50 %.1f ms, p99 %.1f ms" % (serve.get("p50_ms", 0), serve.get("p99_ms", 0)))
-    if "serving_full" in legs:
-        serve_full = run_serving_configured(args, torch, sg, workloads)
-        log("serving (configured lengths): p50 %.1f ms, p99 %.1f ms, %.1f updates/ns"
-            % (serve_full.get("p50_ms", 0), serve_full.get("p99_ms", 0), serve_full["updates_per_ns"]))
+    serve_legs = [x for x in ("serving", "serving_full") if x in legs]
+    if serve_legs and not args.serve_child:
+        serve, serve_full = run_serving_child(args, serve_legs)
+    else:
+        if "serving" in legs:
+            serve = run_serving(args, torch, sg, workloads)
+            log("serving: p50 %.1f ms, p99 %.1f ms" % (serve.get("p50_ms", 0), serve.get("p99_ms", 0)))
+        if "serving_full" in legs:
+            serve_full = run_serving_configured(args, torch, sg, workloads)
+            log("serving (configured lengths): p50 %.1f ms, p99 %.1f ms, %.1f updates/ns"
+                % (serve_full.get("p50_ms", 0), serve_full.get("p99_ms", 0), serve_full["updates_per_ns"]))
     if vb is None:
         print(json.dumps({"legs": dict(plain=plain, sk=sk, sk_gauss=sk_gauss, uneven=uneven, rrbg=rrbg,
                                        multispin=multispin, window=window,

@@ -18,6 +18,7 @@ from __future__ import annotations
 import dataclasses
 import os
 import math
+import threading
 import time
 from typing import Dict, List, Optional
 
@@ -93,17 +94,34 @@ def run_alone(req, flags: int = MEASURE_OBS | MEASURE_SPINS) -> dict:
         sg_free(ctx)
 
 
+def estimate_device_s(kind: str, n: int, sweeps: int) -> float:
+    """Coarse device time of one run with its chains whole (MI355X: a VB
+    chain streams its graph at about 0.8 ns per spin and sweep; an SK chain
+    takes about 100 us per sweep at N = 4096, growing as N^2).  Only used to
+    order batches, longest first."""
+    if kind == "vb":
+        return sweeps * 0.8e-9 * n
+    return sweeps * 100e-6 * (n / 4096.0) ** 2
+
+
 def select_batch(pending, now: float, time_scale: float, used: int, active_requests: int, budget: int,
                  max_batch: int, max_active: int):
-    """The next batch: requests that have arrived by `now` with the same
-    (kind, sweeps) as the oldest arrived one, in arrival order, as long as the
-    batch stays within max_batch, the slot limit and the HBM budget (a batch
-    always gets its first request when nothing else is running).  Returns
-    (batch, its footprint in bytes)."""
+    """The next batch: of the requests that have arrived by `now`, the
+    (kind, sweeps) class whose longest run takes longest on the device
+    (longest first, so that a burst ends as early as it can; a class that
+    arrived earlier wins ties, and requests arriving one at a time are taken
+    in arrival order), its requests in arrival order as long as the batch
+    stays within max_batch, the slot limit and the HBM budget (a batch always
+    gets its first request when nothing else is running).  Returns (batch,
+    its footprint in bytes)."""
     arrived = [r for r in pending if r.arrival * time_scale <= now]
     if not arrived:
         return [], 0
-    key = (arrived[0].kind, arrived[0].sweeps)
+    longest: Dict[tuple, float] = {}
+    for r in arrived:
+        k = (r.kind, r.sweeps)
+        longest[k] = max(longest.get(k, 0.0), estimate_device_s(r.kind, r.n, r.sweeps))
+    key = max(longest, key=lambda k: longest[k])
     batch, fp_sum = [], 0
     for r in arrived:
         if (r.kind, r.sweeps) != key:
@@ -138,11 +156,19 @@ class AgingServer:
     submission order: a batch whose sweeps are all enqueued at admission
     then holds back every batch queued behind it on the same queue.  So the
     pool defaults to one stream per hardware queue (n_streams = None), and a
-    larger pool wants GPU_MAX_HW_QUEUES raised before the first HIP call."""
+    larger pool wants GPU_MAX_HW_QUEUES raised before the first HIP call.
+
+    A VB batch whose longest run is estimated at `split_min_s` seconds or
+    more may split its large graphs over several workgroups; such batches
+    are created one at a time in admission order (the worker threads take
+    turns): a context reserves the workgroups of its split units from a
+    process-wide budget when it is created, so the batch admitted first, the
+    longest, gets them first.  Shorter VB batches keep every unit whole
+    (a split would save them little) and are created at once."""
 
     def __init__(self, hbm_budget: int = 32 << 30, max_active: int = 64, chunk_sweeps: int = 256,
                  n_streams: Optional[int] = None, flags: int = MEASURE_OBS | MEASURE_SPINS,
-                 max_batch: int = 64):
+                 max_batch: int = 64, split_min_s: float = 0.25):
         import torch
         if n_streams is None:
             n_streams = hw_queues()
@@ -153,20 +179,37 @@ class AgingServer:
         self.chunk = max(1, int(chunk_sweeps))
         self.flags = flags
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
+        self.split_min_s = float(split_min_s)
+        self._turn = threading.Condition()
+        self._tickets = 0      # VB batches admitted that may split
+        self._created = 0      # of those, the ones whose context creation has ended
 
     def _take_batch(self, pending, now, time_scale, used, active_requests):
         return select_batch(pending, now, time_scale, used, active_requests, self.budget, self.max_batch,
                             self.max_active)
 
-    def _start(self, batch, stream):
-        """Worker: builds the batch's context and enqueues all its sweeps on
+    def _create(self, batch, ticket):
+        if batch[0].kind == "sk":
+            return sg_create_sk([descriptor(r) for r in batch], t_max=batch[0].sweeps)
+        if ticket is None:
+            return sg_create_vb([descriptor(r) for r in batch], t_max=batch[0].sweeps, split_members=1)
+        with self._turn:
+            self._turn.wait_for(lambda: self._created == ticket)
+        try:
+            return sg_create_vb([descriptor(r) for r in batch], t_max=batch[0].sweeps)
+        finally:
+            with self._turn:
+                self._created += 1
+                self._turn.notify_all()
+
+    def _start(self, batch, stream, ticket=None):
+        """Worker: builds the batch's context (a VB batch that may split:
+        when its turn `ticket` comes) and enqueues all its sweeps on
         `stream`; returns (context, start event, completion event, host time
         when everything was enqueued)."""
         torch = self.torch
         with torch.cuda.stream(stream):
-            descs = [descriptor(r) for r in batch]
-            make = sg_create_vb if batch[0].kind == "vb" else sg_create_sk
-            ctx = make(descs, t_max=batch[0].sweeps)
+            ctx = self._create(batch, ticket)
             try:
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev0.record(stream)
@@ -192,6 +235,7 @@ class AgingServer:
         used = 0
         results: List[Result] = []
         pool = ThreadPoolExecutor(max_workers=len(self.streams))
+        finisher = ThreadPoolExecutor(max_workers=len(self.streams))
         t0 = time.perf_counter()
         try:
             while pending or batches:
@@ -208,24 +252,38 @@ class AgingServer:
                     ids = set(id(r) for r in batch)
                     pending = [r for r in pending if id(r) not in ids]
                     si = free.pop(0)
-                    fut = pool.submit(self._start, batch, self.streams[si])
+                    ticket = None
+                    if batch[0].kind == "vb" and max(estimate_device_s(r.kind, r.n, r.sweeps)
+                                                     for r in batch) >= self.split_min_s:
+                        ticket = self._tickets
+                        self._tickets += 1
+                    # the pool starts tasks in submission order, so a VB
+                    # batch's turn never waits for one submitted after it
+                    fut = pool.submit(self._start, batch, self.streams[si], ticket)
                     batches.append(dict(reqs=batch, fut=fut, si=si, fp=fp, admitted=now))
                     used += fp
                     progressed = True
-                # completion: built, and its stream has run every sweep
+                # completion: built, and its stream has run every sweep; the
+                # batch is then measured and released on a worker thread, so
+                # that a measurement waiting on its stream (a hardware queue
+                # shared with another batch's sweeps) holds up no other batch
                 for b in list(batches):
-                    if not b["fut"].done():
+                    if "done" not in b:
+                        if not b["fut"].done():
+                            continue
+                        ctx, ev0, ev, t_built = b["fut"].result()
+                        if not ev.query():
+                            continue
+                        b["built"] = t_built - t0
+                        b["done"] = finisher.submit(self._finish, ctx, ev0, ev, self.streams[b["si"]], t0)
+                        progressed = True
                         continue
-                    ctx, ev0, ev, t_built = b["fut"].result()
-                    if not ev.query():
+                    if not b["done"].done():
                         continue
-                    obs = sg_measure(ctx, self.flags, stream=self.streams[b["si"]])
-                    sg_free(ctx)
-                    fin = time.perf_counter() - t0
-                    dev = ev0.elapsed_time(ev) * 1e-3
+                    obs, dev, fin = b["done"].result()
                     for i, req in enumerate(b["reqs"]):
                         results.append(Result(req.rid, req.kind, req.n, req.sweeps, req.arrival * time_scale,
-                                              b["admitted"], fin, _slice(obs, i), built=t_built - t0, device=dev))
+                                              b["admitted"], fin, _slice(obs, i), built=b["built"], device=dev))
                     used -= b["fp"]
                     free.append(b["si"])
                     batches.remove(b)
@@ -240,6 +298,12 @@ class AgingServer:
         finally:
             # release what is still in flight (after a time limit or an error)
             for b in batches:
+                if "done" in b:
+                    try:
+                        b["done"].result()
+                    except BaseException:
+                        pass
+                    continue
                 try:
                     ctx, _, ev, _ = b["fut"].result()
                 except BaseException:
@@ -247,7 +311,17 @@ class AgingServer:
                 ev.synchronize()
                 sg_free(ctx)
             pool.shutdown(wait=True)
+            finisher.shutdown(wait=True)
         return results
+
+    def _finish(self, ctx, ev0, ev, stream, t0):
+        """Worker: measures a finished batch on its stream and releases its
+        context; returns (observables, device seconds, finish time)."""
+        try:
+            obs = sg_measure(ctx, self.flags, stream=stream)
+        finally:
+            sg_free(ctx)
+        return obs, ev0.elapsed_time(ev) * 1e-3, time.perf_counter() - t0
 
 
 def _slice(obs: dict, i: int) -> dict:
