@@ -450,6 +450,18 @@ def run_window(args, torch, sg, workloads):
                               window_bytes_per_update=round(win_b / n_total, 3)))
 
 
+_SERVE_STREAMS = []
+
+
+def serve_streams(torch):
+    """The serving legs' stream pool, shared by their servers: every stream
+    HIP has seen keeps a hardware queue, and a process with more queues than
+    the hardware schedules at once runs every kernel slower."""
+    if not _SERVE_STREAMS:
+        _SERVE_STREAMS.extend(torch.cuda.Stream() for _ in range(SERVE_STREAMS))
+    return list(_SERVE_STREAMS)
+
+
 def run_serving(args, torch, sg, workloads):
     """Serving: Poisson arrivals, 70% VB (N in [2^12, 2^20]) / 30% SK (N in
     [512, 8192]), T ~ U[0.5, 0.9]; run lengths reduced to 2^8..2^10 sweeps so
@@ -460,8 +472,7 @@ def run_serving(args, torch, sg, workloads):
     for i, r in enumerate(reqs):
         r.sweeps = rng_len[i % 3]
     server = serving.AgingServer(hbm_budget=64 << 30, max_active=64, chunk_sweeps=256,
-                                 n_streams=SERVE_STREAMS,
-                                 flags=sg.MEASURE_OBS)
+                                 streams=serve_streams(torch), flags=sg.MEASURE_OBS)
     t0 = time.perf_counter()
     results = server.run(reqs, max_wall=120.0)
     el = time.perf_counter() - t0
@@ -505,8 +516,7 @@ def run_serving_configured(args, torch, sg, workloads):
 
     def serve(reqs, max_wall):
         server = serving.AgingServer(hbm_budget=64 << 30, max_active=128, chunk_sweeps=4096,
-                                     n_streams=SERVE_STREAMS,
-                                     flags=sg.MEASURE_OBS)
+                                     streams=serve_streams(torch), flags=sg.MEASURE_OBS)
         t0 = time.perf_counter()
         out = server.run(reqs, max_wall=max_wall)
         return out, time.perf_counter() - t0

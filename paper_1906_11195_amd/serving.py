@@ -168,7 +168,7 @@ class AgingServer:
 
     def __init__(self, hbm_budget: int = 32 << 30, max_active: int = 64, chunk_sweeps: int = 256,
                  n_streams: Optional[int] = None, flags: int = MEASURE_OBS | MEASURE_SPINS,
-                 max_batch: int = 64, split_min_s: float = 0.25):
+                 max_batch: int = 64, split_min_s: float = 0.25, streams=None):
         import torch
         if n_streams is None:
             n_streams = hw_queues()
@@ -178,7 +178,9 @@ class AgingServer:
         self.max_batch = int(max_batch)
         self.chunk = max(1, int(chunk_sweeps))
         self.flags = flags
-        self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
+        # a caller running several servers one after another can hand them
+        # the same streams (each stream HIP has seen holds a hardware queue)
+        self.streams = list(streams) if streams else [torch.cuda.Stream() for _ in range(max(1, n_streams))]
         self.split_min_s = float(split_min_s)
         self._turn = threading.Condition()
         self._tickets = 0      # VB batches admitted that may split
