@@ -4,7 +4,8 @@ Covers several samples with two clones through field recomputations, ragged
 sizes (not multiples of the 64-spin block or of 16), T = inf and T = 0,
 aligned and given starts, given couplings, sweeps split over calls, and the
 full-size SK configuration on a prefix of sweeps with sampled chains, and
-the largest supported sizes."""
+the largest supported sizes, and the sizes around the updaters' one-pass
+capacity."""
 import math
 
 import numpy as np
@@ -102,3 +103,15 @@ def test_sk_largest_sizes(n):
     d = sg.SkDesc(n=n, T=0.5, seed=5, instance_id=0, graph_id=5, recompute_period=4)
     res = run_lib([d], 6, 8)
     assert_instance_equal(res, 0, oracle_sk(d, 6, 8), label="n=%d" % n)
+
+
+@pytest.mark.parametrize("n", [4097, 7168, 7169, 8192])
+def test_sk_updater_pass_boundaries(n):
+    # The updater wavefronts apply a block's flips to 7168 fields per pass
+    # (14 wavefronts x 64 lanes x 8 fields): one pass up to N = 7168, a
+    # second, partly filled one above it; the serving workload's SK sizes
+    # reach 8192.
+    require_gpu()
+    d = sg.SkDesc(n=n, T=0.5, seed=6, instance_id=1, graph_id=6, recompute_period=4)
+    res = run_lib([d], 10, 16)
+    assert_instance_equal(res, 0, oracle_sk(d, 10, 16), label="n=%d" % n)
