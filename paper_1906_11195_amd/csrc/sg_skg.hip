@@ -29,7 +29,13 @@
 namespace sg {
 namespace {
 
-constexpr int kSkgThreads = 256;
+// Threads per chain: in step 3 a thread takes 4 fields at a time, so with
+// 1024 threads the fields of N <= 4096 take one pass and a block's row loads
+// cost one memory latency (with 256 threads, four passes one after another).
+#ifndef SG_SKG_THREADS
+#define SG_SKG_THREADS 1024
+#endif
+constexpr int kSkgThreads = SG_SKG_THREADS;
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct SkgLds {
@@ -92,18 +98,19 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
     unsigned long long acc = 0;   // accepted flips (wave 0, lane 0)
 
     // 1. the coupling tile of a block, T[i][j] = J[p0 + i][p0 + j], is loaded
-    //    into registers (16 floats per thread, 16-byte loads when the rows
+    //    into registers (4096 / threads floats per thread, 16-byte loads when the rows
     //    are 16-byte aligned) while the block before it is decided and
     //    applied, and stored to LDS when its turn comes
-    static_assert(kSkgThreads == 256, "a thread holds 16 floats of a 64 x 64 tile");
-    v4f tv[4];
-    float ts[16];
+    constexpr int TS = 64 * 64 / kSkgThreads, T4 = TS / 4;   // tile floats, 16-byte loads per thread
+    static_assert(TS * kSkgThreads == 64 * 64 && T4 * 4 == TS, "the tile splits evenly into 16-byte parts");
+    v4f tv[T4];
+    float ts[TS];
     auto tile_load = [&](int32_t bb) {
         const int32_t q0 = bb << 6;
         const int32_t mm = min(64, n - q0);
         if (vec4) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < T4; ++k) {
                 const int32_t idx = tid + k * kSkgThreads;
                 const int32_t i = idx >> 4, j = (idx & 15) << 2;
                 const v4f z = {0.f, 0.f, 0.f, 0.f};
@@ -111,7 +118,7 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
+            for (int k = 0; k < TS; ++k) {
                 const int32_t idx = tid + k * kSkgThreads;
                 const int32_t i = idx >> 6, j = idx & 63;
                 ts[k] = (i < mm && j < mm) ? J[(int64_t)(q0 + i) * n + q0 + j] : 0.0f;
@@ -121,13 +128,13 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
     auto tile_store = [&]() {
         if (vec4) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < T4; ++k) {
                 const int32_t idx = tid + k * kSkgThreads;
                 *(v4f*)(L.tile + ((idx >> 4) << 6) + ((idx & 15) << 2)) = tv[k];
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) L.tile[tid + k * kSkgThreads] = ts[k];
+            for (int k = 0; k < TS; ++k) L.tile[tid + k * kSkgThreads] = ts[k];
         }
     };
     if (nsw > 0) tile_load(0);
