@@ -80,6 +80,31 @@ __device__ __forceinline__ bool skg_accept(double x, double beta, uint32_t r)
     return (uint64_t)r < thr;
 }
 
+// The same decision through a per-lane bound on x, fixed by r before the
+// rounds: r < floor(2^32 exp(-2 beta x)) holds iff 2^32 exp(-2 beta x) >=
+// r + 1, i.e. x <= xc = -ln((r + 1) 2^-32) / (2 beta).  Outside a band of
+// relative width 1e-9 around xc (far wider than the rounding of exp, ln and
+// the division) the bound decides; inside it, and for beta = 0 or infinite,
+// the rule itself does, so every decision is that of skg_accept.
+struct SkgBound {
+    double lo, hi;   // accept below lo, reject above hi, else evaluate
+};
+
+__device__ __forceinline__ SkgBound skg_bound(double beta, uint32_t r)
+{
+    if (!(beta > 0.0) || !(beta < 1e300)) return SkgBound{0.0, 1e308};
+    const double xc = -log(((double)r + 1.0) * 0x1p-32) / (2.0 * beta);
+    const double band = 1e-9 * (xc + 1.0);
+    return SkgBound{xc - band, xc + band};
+}
+
+__device__ __forceinline__ bool skg_accept_b(double x, double beta, uint32_t r, const SkgBound& bd)
+{
+    if (x <= 0.0 || x < bd.lo) return true;
+    if (x > bd.hi) return false;
+    return skg_accept(x, beta, r);
+}
+
 __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* __restrict__ chains, int64_t t0,
                                                                 int32_t nsw, int64_t t_max)
 {
@@ -159,10 +184,11 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
                 double h = act ? L.H[p] : 0.0;
                 double sp = act && ((L.bits[p >> 5] >> (p & 31)) & 1u) ? -1.0 : 1.0;
                 const uint32_t r = act ? skg_uniform(ch, t, (uint32_t)p) : 0u;
+                const SkgBound bd = skg_bound(beta, r);
                 int32_t first = 0;   // lanes below `first` are decided
                 int32_t nf = 0;
                 for (;;) {
-                    const bool cand = act && lane >= first && skg_accept(sp * h, beta, r);
+                    const bool cand = act && lane >= first && skg_accept_b(sp * h, beta, r, bd);
                     const unsigned long long mk = __builtin_amdgcn_ballot_w64(cand);
                     if (mk == 0ull) break;
                     const int32_t i = __builtin_ctzll(mk);
