@@ -44,6 +44,9 @@ struct SkgLds {
     float* tile;        // [64][64]: rows of the block's spins, its columns
     int32_t* flips;     // [64]: lane | (new spin -1) << 31, in flip order
     int32_t* nflip;     // [2]
+    uint32_t* rnd;      // [2][64]: a block's acceptance uniforms (two blocks in turn)
+    double* xlo;        // [2][64]: their acceptance bounds (SkgBound)
+    double* xhi;        // [2][64]
 };
 
 __device__ __forceinline__ SkgLds skg_carve(uint8_t* base, int32_t n, int32_t wn)
@@ -60,6 +63,9 @@ __device__ __forceinline__ SkgLds skg_carve(uint8_t* base, int32_t n, int32_t wn
     L.tile = (float*)take(64 * 64 * 4);
     L.flips = (int32_t*)take(64 * 4);
     L.nflip = (int32_t*)take(16);
+    L.rnd = (uint32_t*)take(2 * 64 * 4);
+    L.xlo = (double*)take(2 * 64 * 8);
+    L.xhi = (double*)take(2 * 64 * 8);
     return L;
 }
 
@@ -164,9 +170,25 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
     };
     if (nsw > 0) tile_load(0);
 
+    // The acceptance uniforms of a block's lanes and their bounds on x are
+    // drawn by wavefront 1 while wavefront 0 decides the block before it
+    // (they depend on the sweep and the position only), into the half of
+    // the double buffer that block will read.
+    static_assert(kSkgThreads >= 128, "wavefront 1 draws the next block's uniforms");
+    auto draw = [&](int32_t bb, uint32_t tt, int32_t half) {
+        const int32_t p = (bb << 6) + lane;
+        const uint32_t r = p < n ? skg_uniform(ch, tt, (uint32_t)p) : 0u;
+        const SkgBound bd = skg_bound(beta, r);
+        L.rnd[half * 64 + lane] = r;
+        L.xlo[half * 64 + lane] = bd.lo;
+        L.xhi[half * 64 + lane] = bd.hi;
+    };
+    if (nsw > 0 && wave == 1) draw(0, (uint32_t)t0, 0);
+    int32_t half = 0;   // the buffer half of the current block
+
     for (int32_t s = 0; s < nsw; ++s) {
         const uint32_t t = (uint32_t)(t0 + s);
-        for (int32_t b = 0; b < NB; ++b) {
+        for (int32_t b = 0; b < NB; ++b, half ^= 1) {
             const int32_t p0 = b << 6;
             const int32_t m = min(64, n - p0);
             tile_store();
@@ -183,8 +205,11 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
                 const int32_t p = p0 + lane;
                 double h = act ? L.H[p] : 0.0;
                 double sp = act && ((L.bits[p >> 5] >> (p & 31)) & 1u) ? -1.0 : 1.0;
-                const uint32_t r = act ? skg_uniform(ch, t, (uint32_t)p) : 0u;
-                const SkgBound bd = skg_bound(beta, r);
+                const uint32_t r = L.rnd[half * 64 + lane];
+                const SkgBound bd{L.xlo[half * 64 + lane], L.xhi[half * 64 + lane]};
+                // a lane flips at most once in its block, so the new spin
+                // of a flipping lane is the opposite of its spin here
+                const unsigned long long was_neg = __builtin_amdgcn_ballot_w64(act && sp < 0.0);
                 int32_t first = 0;   // lanes below `first` are decided
                 int32_t nf = 0;
                 for (;;) {
@@ -193,7 +218,7 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
                     if (mk == 0ull) break;
                     const int32_t i = __builtin_ctzll(mk);
                     if (lane == i) sp = -sp;
-                    const double si = __shfl(sp, i);   // the new spin of lane i
+                    const double si = ((was_neg >> i) & 1ull) ? 1.0 : -1.0;   // the new spin of lane i
                     if (lane > i) h = h + (2.0 * si) * (double)L.tile[i * 64 + lane];
                     if (lane == 0) L.flips[nf] = i | (si < 0.0 ? (int32_t)0x80000000 : 0);
                     ++nf;
@@ -207,6 +232,11 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
                     L.nflip[0] = nf;
                     acc += (unsigned long long)nf;
                 }
+            } else if (wave == 1) {
+                if (b + 1 < NB)
+                    draw(b + 1, t, half ^ 1);
+                else if (s + 1 < nsw)
+                    draw(0, t + 1u, half ^ 1);
             }
             __syncthreads();
             // 3. the block's flips reach every other field, in flip order
@@ -399,7 +429,7 @@ size_t skg_lds_bytes(int32_t n)
 {
     const size_t wn = (size_t)(n + 31) / 32;
     auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
-    return r16((size_t)n * 8) + r16((wn + 2) * 4) + 64 * 64 * 4 + 64 * 4 + 16;
+    return r16((size_t)n * 8) + r16((wn + 2) * 4) + 64 * 64 * 4 + 64 * 4 + 16 + 2 * 64 * 4 + 2 * 2 * 64 * 8;
 }
 
 hipError_t skg_sweep(const SkChain* chains, int n_chains, size_t lds_bytes, int64_t t0, int32_t n_sweeps,
