@@ -696,12 +696,21 @@ def main():
         print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
         return
     sg.library()
+    legs = set() if args.only_vb else set(x.strip() for x in args.legs.split(","))
+    # the serving legs run first, in a child process, while this process
+    # holds next to no hardware queues (the queues of all processes on the
+    # device share the hardware's scheduler: with this process's queues of
+    # the other legs beside the child's, the capacity run took 29-31 s
+    # instead of 21)
+    serve = serve_full = None
+    serve_legs = [x for x in ("serving", "serving_full") if x in legs]
+    if serve_legs and not args.serve_child:
+        serve, serve_full = run_serving_child(args, serve_legs)
     vb = None
     if not args.skip_headline:
         vb = run_vb_batched(args, torch, sg, workloads)
         log("VB batched: %.1f updates/ns" % vb["value"])
-    plain = sk = uneven = rrbg = serve = window = serve_full = sk_gauss = multispin = None
-    legs = set() if args.only_vb else set(x.strip() for x in args.legs.split(","))
+    plain = sk = uneven = rrbg = window = sk_gauss = multispin = None
     if "plain" in legs:
         plain = run_vb_plain(args, torch, sg, workloads)
         log("VB plain: p50 %.2f ms" % plain["p50_ms"])
@@ -724,10 +733,7 @@ def main():
     if "window" in legs:
         window = run_window(args, torch, sg, workloads)
         log("VB windowed C: %.1f updates/ns" % window["updates_per_ns"])
-    serve_legs = [x for x in ("serving", "serving_full") if x in legs]
-    if serve_legs and not args.serve_child:
-        serve, serve_full = run_serving_child(args, serve_legs)
-    else:
+    if args.serve_child:
         if "serving" in legs:
             serve = run_serving(args, torch, sg, workloads)
             log("serving: p50 %.1f ms, p99 %.1f ms" % (serve.get("p50_ms", 0), serve.get("p99_ms", 0)))
