@@ -15,7 +15,8 @@
 // 32-bit uniform as for binary couplings.
 //
 // One workgroup runs one chain, visiting i = 0..N-1 in blocks of 64 spins:
-//  1. the block's 64 x 64 coupling tile is staged in LDS;
+//  1. the block's 64 x 64 coupling tile is staged in LDS (loaded during the
+//     block before it);
 //  2. one wavefront decides the block in rounds: every undecided lane tests
 //     its move with its current field; the first lane that accepts flips,
 //     the lanes before it keep their spins, and the lanes after it add the
@@ -131,7 +132,7 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
     // 1. the coupling tile of a block, T[i][j] = J[p0 + i][p0 + j], is loaded
     //    into registers (4096 / threads floats per thread, 16-byte loads when the rows
     //    are 16-byte aligned) while the block before it is decided and
-    //    applied, and stored to LDS when its turn comes
+    //    applied, and stored to LDS at the end of that block
     constexpr int TS = 64 * 64 / kSkgThreads, T4 = TS / 4;   // tile floats, 16-byte loads per thread
     static_assert(TS * kSkgThreads == 64 * 64 && T4 * 4 == TS, "the tile splits evenly into 16-byte parts");
     v4f tv[T4];
@@ -183,7 +184,11 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
         L.xlo[half * 64 + lane] = bd.lo;
         L.xhi[half * 64 + lane] = bd.hi;
     };
-    if (nsw > 0 && wave == 1) draw(0, (uint32_t)t0, 0);
+    if (nsw > 0) {
+        tile_store();
+        if (wave == 1) draw(0, (uint32_t)t0, 0);
+    }
+    __syncthreads();
     int32_t half = 0;   // the buffer half of the current block
 
     for (int32_t s = 0; s < nsw; ++s) {
@@ -191,10 +196,10 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
         for (int32_t b = 0; b < NB; ++b, half ^= 1) {
             const int32_t p0 = b << 6;
             const int32_t m = min(64, n - p0);
-            tile_store();
-            __syncthreads();
             // the next block's tile (the first block of the next sweep after
-            // the last one)
+            // the last one), stored to LDS once this block's decisions no
+            // longer read the tile (after its flips are applied)
+            const bool next_tile = b + 1 < NB || s + 1 < nsw;
             if (b + 1 < NB)
                 tile_load(b + 1);
             else if (s + 1 < nsw)
@@ -301,6 +306,7 @@ __global__ void __launch_bounds__(kSkgThreads) skg_sweep_kernel(const SkChain* _
                     }
                 }
             }
+            if (next_tile) tile_store();
             __syncthreads();
         }
         const int64_t tn = t0 + s + 1;
