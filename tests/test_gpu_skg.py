@@ -122,3 +122,14 @@ def test_skg_corrupted_field_is_reported_by_the_recompute():
     # mixing real and binary couplings in one context is refused
     with pytest.raises(sg.SgError):
         sg.sg_create_sk([d, sg.SkDesc(n=n, T=0.5, seed=3, instance_id=3)], t_max=8)
+
+
+@pytest.mark.parametrize("n", [4100, 8192, 16384])
+def test_skg_fields_beyond_one_pass(n):
+    # a thread applies a block's flips to 4 fields at a time, so the 1024
+    # threads of a chain cover 4096 fields per pass: 2 passes at N = 4100
+    # and 8192, 4 at the largest size (whose fields fill most of the LDS)
+    require_gpu()
+    d = sg.SkDesc(n=n, T=0.5, seed=8, instance_id=0, graph_id=0, Jf=gaussian_couplings(n, seed=n + 1),
+                  recompute_period=4)
+    check([d], [3, 3], 8)
