@@ -625,7 +625,11 @@ def run_serving_child(args, legs):
            "--serve-full-requests", str(args.serve_full_requests), "--serve-max-wall", str(args.serve_max_wall)]
     out = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, text=True)
     if out.returncode != 0:
-        raise RuntimeError("serving legs failed in the child process (exit %d)" % out.returncode)
+        # the other legs and the headline still run; the failure is reported
+        # in place of the serving figures
+        err = {"error": "serving legs failed in the child process (exit %d)" % out.returncode}
+        log(err["error"])
+        return (err if "serving" in legs else None), (err if "serving_full" in legs else None)
     d = json.loads(out.stdout.strip().splitlines()[-1])["legs"]
     return d.get("serving"), d.get("serving_full")
 
