@@ -21,6 +21,7 @@
 #include "sg.h"
 #include "sg_internal.h"
 #include "sg_ledger.h"
+#include "sg_split_plan.h"
 #include "sg_philox.h"
 
 using namespace sg;
@@ -368,14 +369,6 @@ struct Arena {
 
 namespace {
 SplitLedger g_split_ledger;   // split-unit members held per device, all contexts
-// automatic split of VB units over workgroups (members): the least cost (spins
-// x (10 + chains)) a member carries with at most two, at most eight and more
-// split units (about 8, 14 and 28 us of a sweep on MI355X), and the most
-// members of one unit
-constexpr int64_t kSplitMemberCostFew = 75000;
-constexpr int64_t kSplitMemberCostSome = 130000;
-constexpr int64_t kSplitMemberCostMany = 260000;
-constexpr int kSplitMaxMembers = 32;
 }  // namespace
 
 struct sg_ctx {
@@ -888,26 +881,7 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
     // resident at once next to other work, and an automatic plan takes at
     // most a quarter of the CUs, so that two large contexts built at the same
     // time (a server's batches) both split their largest units.
-    // A unit's cost per sweep is dominated by its graph (adjacency stream and
-    // spin words per vertex), which its chains share; a chain adds about a
-    // tenth of that (whole units, us per sweep: one chain of 985767 spins 792,
-    // six chains of 65536 spins 82), so the plan weighs a unit as n (10 + chains).
-    // Splitting shortens a launch only if no unit left whole outlasts the
-    // split ones, so the automatic choice splits the units far above a CU's
-    // share (by cost) only when all of them get at least two members, or
-    // else the largest group of them with three times the cost of every unit
-    // left whole.  Their members are shared out in proportion to cost, so
-    // that every member of every split unit carries about the same part of a
-    // sweep, but no member less than a floor that rises with the number of
-    // split units: members of many split units meet at barriers at the same
-    // time, and thin members then wait more than they compute.  Measured, us
-    // per sweep: graphs of 65536 spins with 6 chains, 1 graph 13 members 33,
-    // 4 graphs 8 members 41 (4: 48), 16 graphs 4 members 57 (6: 61, 8: 73),
-    // 64 graphs 2 members 78 (whole: 82; more members than a quarter of the
-    // CUs, so they stay whole); one request of 985767 spins with 2 chains (two
-    // units), 8 members each 153, 16 97, 32 78, 64 82.  At most
-    // kSplitMaxMembers per unit, and at least two 64-position chunks per
-    // wavefront of the largest class per member.
+    // Members per unit: plan_split (sg_split_plan.h), by cost n (10 + chains).
     // opts.split_members: 0 automatic, 1 never, k >= 2 every unit that has
     // the chunks for k members (tests, tuning).  No effect on any result.
     {
@@ -924,49 +898,18 @@ void create_vb(sg_ctx* c, const sg_vb_desc* d, int32_t count, const sg_opts* o)
         // together stay within half of the CUs (members reserved while their
         // context lives, so that all of them can be resident at once)
         c->split_held = g_split_ledger.reserve(c->device, n_cu / 2, [&](int avail) {
-            int budget = forced == 0 ? std::min(avail, n_cu / 4) : avail;
-            std::vector<size_t> by_cost(plan.size());
-            for (size_t i = 0; i < plan.size(); ++i) by_cost[i] = i;
-            std::stable_sort(by_cost.begin(), by_cost.end(),
-                             [&](size_t a, size_t b) { return cost_of(plan[a]) > cost_of(plan[b]); });
-            size_t n_auto = 0;
-            if (forced == 0) {
-                size_t cand = 0;
-                while (cand < by_cost.size() && !plan[by_cost[cand]].resident &&
-                       cost_of(plan[by_cost[cand]]) >= 2 * share)
-                    ++cand;
-                for (size_t m = std::min(cand, (size_t)(budget / 2)); m >= 1; --m) {
-                    const int64_t rest = by_cost.size() > m ? cost_of(plan[by_cost[m]]) : 0;
-                    if (m == cand || cost_of(plan[by_cost[m - 1]]) >= 3 * rest) {
-                        n_auto = m;
-                        break;
-                    }
-                }
-            }
-            int64_t split_cost = 0;
-            for (size_t r = 0; r < n_auto; ++r) split_cost += cost_of(plan[by_cost[r]]);
-            const int64_t floor_cost = n_auto <= 2 ? kSplitMemberCostFew
-                                       : n_auto <= 8 ? kSplitMemberCostSome : kSplitMemberCostMany;
-            const int64_t per_member = std::max<int64_t>(
-                {share, (split_cost + budget - 1) / std::max(1, budget), floor_cost});
-            for (size_t r = 0; r < by_cost.size(); ++r) {
-                UnitPlan& u = plan[by_cost[r]];
-                if (forced == 1 || u.resident || (forced == 0 && r >= n_auto)) continue;
-                const VbGraph& g = graphs[(size_t)u.group];
+            const int budget = forced == 0 ? std::min(avail, n_cu / 4) : avail;
+            std::vector<SplitUnit> su(plan.size());
+            for (size_t i = 0; i < plan.size(); ++i) {
+                const VbGraph& g = graphs[(size_t)plan[i].group];
                 int32_t maxcls = 0;
                 for (int32_t k = 0; k < g.ncls; ++k) maxcls = std::max(maxcls, g.cls[(size_t)k + 1] - g.cls[(size_t)k]);
-                const int64_t chunk_cap = ((maxcls + 63) / 64) / (2 * (u.threads / 64));
-                int64_t want = forced >= 2 ? forced
-                                           : std::min<int64_t>(kSplitMaxMembers,
-                                                               (cost_of(u) + per_member / 2) / per_member);
-                want = std::min<int64_t>(want, std::min<int64_t>(chunk_cap, budget));
-                if (want >= 2) {
-                    u.members = (int)want;
-                    budget -= (int)want;
-                }
+                su[i] = SplitUnit{cost_of(plan[i]), plan[i].resident,
+                                  ((maxcls + 63) / 64) / (2 * (plan[i].threads / 64))};
             }
-            int used = 0;
-            for (const auto& u : plan) used += u.members > 1 ? u.members : 0;
+            std::vector<int> members;
+            const int used = plan_split(su, share, budget, forced, members);
+            for (size_t i = 0; i < plan.size(); ++i) plan[i].members = members[i];
             return used;
         });
     }
